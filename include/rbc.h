@@ -1,0 +1,192 @@
+/*
+ * rbc.h -- C ABI of the MI355X (gfx950) Random Ball Cover / brute-force
+ * nearest-neighbour library (librbc.so).
+ *
+ * The library implements the brute-force primitive BF(Q, X) of Cayton,
+ * "Accelerating Nearest Neighbor Search on Manycore Systems" (Sec. 3: for
+ * every query, the distance to every database point followed by a
+ * per-query comparison), and the Random Ball Cover built from it (Sec. 4:
+ * representatives, ownership lists L_r, radii psi_r; Sec. 5.1 one-shot
+ * search; Sec. 5.2 exact search with pruning rules (1) and (2)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are row-major float32 in DEVICE memory: row i of an m x d
+ *    matrix A starts at A + i * lda, lda >= d.  Queries Q (m x d) and the
+ *    database X (n x d) are owned by the caller.
+ *  - Outputs are DEVICE arrays owned by the caller: out_idx (m x k, int64,
+ *    row-major) and out_dist (m x k, float32).  For every query the k
+ *    results are sorted ascending by (distance, database row id): a tie in
+ *    distance is won by the lower row id.  out_dist holds rho itself:
+ *    Euclidean distance for RBC_L2 (not squared), sum of absolute
+ *    differences for RBC_L1.  out_idx holds the row of X.
+ *  - Every call is asynchronous on the given HIP stream (NULL = the null
+ *    stream).  The return value reports argument validation and kernel
+ *    launch only; a device fault surfaces at the caller's next
+ *    synchronisation.  No call synchronises the stream except rbc_build
+ *    (which returns a finished index) and rbc_free.
+ *  - No exception crosses the ABI.  A non-zero return is an rbc_status;
+ *    rbc_last_error() then describes it (thread-local string).
+ *  - m == 0 is a no-op returning RBC_OK.  Inputs must be finite.
+ *  - Exactness: results equal exhaustive search in exact arithmetic on the
+ *    float32 inputs (ranking by (distance, id)); distances are accurate to
+ *    a few float32 ulps.  Candidates are ranked with a fast float32
+ *    contraction, re-scored directly, near-ties re-ranked in float64, and a
+ *    query whose shortlist cannot be certified is searched again
+ *    exhaustively in float64.
+ */
+#ifndef RBC_H_
+#define RBC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Metric rho (Sec. 4; the l1 form is the one written out in Sec. 6). */
+typedef enum { RBC_L2 = 0, RBC_L1 = 1 } rbc_metric;
+
+/* Arithmetic of the distance contraction.  RBC_FP32 is the only precision
+ * of this version; the others return RBC_EUNSUPPORTED. */
+typedef enum { RBC_FP32 = 0, RBC_BF16 = 1, RBC_FP8_E4M3 = 2 } rbc_precision;
+
+/* Ownership rule of the index (Sec. 4): RBC_EXACT -- each point is owned by
+ * its nearest representative (lists partition X); RBC_ONESHOT -- each
+ * representative owns its s nearest database points (lists overlap). */
+typedef enum { RBC_EXACT = 0, RBC_ONESHOT = 1 } rbc_mode;
+
+typedef enum {
+    RBC_OK = 0,
+    RBC_EINVAL = -1,        /* an argument is out of range or a pointer is NULL */
+    RBC_ENOMEM = -2,        /* device allocation failed (rbc_build only) */
+    RBC_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    RBC_EUNSUPPORTED = -4,  /* valid request outside what this build implements */
+    RBC_EWORKSPACE = -5     /* workspace NULL or smaller than the size query says */
+} rbc_status;
+
+/* Largest k accepted by bf_search / rbc_search. */
+#define RBC_MAX_K 1024
+/* Largest dimension accepted. */
+#define RBC_MAX_D 4096
+
+/* Number of int64 counters written to rbc_search_opts.dev_stats. */
+#define RBC_STATS_LEN 8
+/* Counter slots (added to, never cleared by the library). */
+#define RBC_STAT_FALLBACK   0  /* queries re-searched exhaustively in float64 */
+#define RBC_STAT_NEARTIE    1  /* shortlist entries re-ranked in float64 */
+#define RBC_STAT_PAIRS      2  /* (query, point) pairs scored by the main kernel */
+#define RBC_STAT_LISTS      3  /* (query, list) pairs kept by the pruning rules */
+#define RBC_STAT_CAND       4  /* (query, point) pairs inside kept lists */
+
+/* Per-call search options.  Pass NULL for the defaults. */
+typedef struct rbc_search_opts {
+    int32_t precision;  /* rbc_precision; default RBC_FP32 */
+    int32_t shortlist;  /* per-query shortlist length c (0 = automatic); rounded up
+                           to one of 4, 8, 16, 32, 64 and at least k + 3 */
+    int32_t splits;     /* database splits per query block (0 = automatic) */
+    int32_t flags;      /* reserved, must be 0 */
+    int64_t* dev_stats; /* optional DEVICE array of RBC_STATS_LEN int64 counters */
+} rbc_search_opts;
+
+/* Index construction parameters. */
+typedef struct rbc_build_params {
+    int32_t mode;            /* rbc_mode */
+    int32_t metric;          /* rbc_metric */
+    int64_t n_r;             /* number of representatives, 1 <= n_r <= n */
+    int64_t s;               /* one-shot list length, 1 <= s <= n (ignored for RBC_EXACT) */
+    uint64_t seed;           /* seed of the representative draw when rep_idx is NULL */
+    const int64_t* rep_idx;  /* optional HOST array of n_r distinct row ids of X;
+                                copied and sorted ascending by the library */
+} rbc_build_params;
+
+typedef struct rbc_index rbc_index; /* opaque; owns its device memory */
+
+/*
+ * bf_search -- the brute-force primitive BF(Q, X) (Sec. 3), k-NN form: the
+ * distance step (a query-by-database tile; for RBC_L2 the ranking value
+ * ||x||^2 - 2 q.x is a dense contraction run on the matrix cores) followed
+ * by the comparison step (a per-query top-k).
+ *   Q: m x d (ldq), X: n x d (ldx) device float32; 1 <= k <= min(n, RBC_MAX_K).
+ *   workspace: device memory of at least bf_search_workspace_size() bytes
+ *   (same m, n, d, ldq, ldx, metric, k, opts), used only by the work the
+ *   call queues on `stream`.  Q and X must be 16-byte aligned.
+ * Errors: RBC_EINVAL for d < 1, n < 1, k < 1, k > n, ldq < d, ldx < d,
+ * m < 0, NULL pointers with m > 0; RBC_EUNSUPPORTED for d > RBC_MAX_D,
+ * k > RBC_MAX_K, n >= 2^31, or a precision other than RBC_FP32;
+ * RBC_EWORKSPACE when the workspace is too small.
+ */
+int bf_search_workspace_size(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx,
+                             int32_t metric, int32_t k, const rbc_search_opts* opts,
+                             size_t* bytes);
+int bf_search(const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n, int64_t ldx,
+              int32_t d, int32_t metric, int32_t k, const rbc_search_opts* opts,
+              int64_t* out_idx, float* out_dist, void* workspace, size_t ws_bytes,
+              void* hip_stream);
+
+/*
+ * rbc_build -- build a Random Ball Cover over X (Sec. 4).
+ *   RBC_EXACT: ownership by BF(X, R) with k = 1 (ties to the lower
+ *   representative position), lists stored as contiguous row ranges of a
+ *   permuted copy of X (ascending row id inside a list), psi_r = the largest
+ *   distance from r to a point it owns.
+ *   RBC_ONESHOT: each representative's s nearest database points (ties to
+ *   the lower row id), psi_r = the s-th of those distances.
+ * Representatives are the caller's rep_idx, or n_r distinct rows drawn
+ * uniformly from `seed`.  The index copies what it needs: X may be freed
+ * when the call returns.  The call synchronises `stream`.
+ * Errors: RBC_EINVAL (bad sizes, duplicate or out-of-range rep ids, s > n,
+ * NULL pointers); RBC_ENOMEM; RBC_EUNSUPPORTED as for bf_search.
+ */
+int rbc_build(const float* X, int64_t n, int64_t ldx, int32_t d,
+              const rbc_build_params* params, void* hip_stream, rbc_index** out);
+
+/*
+ * rbc_search -- search an index (Sec. 5.2 for RBC_EXACT, Sec. 5.1 for
+ * RBC_ONESHOT).  Exact mode returns exactly the k nearest neighbours; the
+ * k-NN form of the pruning rules is: with gamma_1 <= ... <= gamma_k the k
+ * smallest distances from q to the representatives, list L_r is skipped
+ * when rho(q,r) - psi_r > gamma_k (rule 1) or rho(q,r) > 2 gamma_k +
+ * gamma_1 (rule 2); bounds are widened by the float32 error of the
+ * computed distances.  One-shot mode returns the k nearest points of q's
+ * nearest representative's list (k <= s).
+ *   Q: m x d (ldq) device float32; outputs as for bf_search; `workspace`
+ *   of at least rbc_search_workspace_size() bytes.  Concurrent calls on
+ *   different streams with different workspaces are safe (the index is
+ *   read-only after rbc_build).
+ */
+int rbc_search_workspace_size(const rbc_index* index, int64_t m, int32_t k,
+                              const rbc_search_opts* opts, size_t* bytes);
+int rbc_search(const rbc_index* index, const float* Q, int64_t m, int64_t ldq, int32_t k,
+               const rbc_search_opts* opts, int64_t* out_idx, float* out_dist,
+               void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * rbc_index_info -- sizes of a built index (any output pointer may be NULL).
+ */
+int rbc_index_info(const rbc_index* index, int64_t* n, int32_t* d, int64_t* n_r,
+                   int32_t* mode, int32_t* metric, size_t* device_bytes);
+
+/*
+ * rbc_index_export -- copy index arrays to HOST buffers (any may be NULL):
+ *   rep_idx[n_r] (int64, ascending), psi[n_r] (float64),
+ *   list_off[n_r + 1] (int64; exact mode: list r is entries
+ *   list_off[r] .. list_off[r+1]-1 of list_ids; one-shot: r * s),
+ *   list_ids[n (exact) or n_r * s (one-shot)] (int64 row ids of X).
+ * Synchronises the device.
+ */
+int rbc_index_export(const rbc_index* index, int64_t* rep_idx, double* psi,
+                     int64_t* list_off, int64_t* list_ids);
+
+/* rbc_free -- release an index (NULL is a no-op).  Synchronises the device. */
+void rbc_free(rbc_index* index);
+
+/* rbc_last_error -- message for the last non-OK return on this thread. */
+const char* rbc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBC_H_ */

@@ -1,0 +1,247 @@
+"""Python binding of librbc (include/rbc.h): argument marshalling only.
+
+Every step of a search runs in the library's HIP kernels; this module passes
+device pointers of torch tensors, the current HIP stream and a workspace
+tensor.  The library must be built (``paper_1103_2635_amd.build.build()``);
+importing the binding without it, or calling it on tensors that are not on a
+GPU, raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbc.so")
+
+L2, L1 = 0, 1
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+EXACT, ONESHOT = 0, 1
+STATS_LEN = 8
+STAT_FALLBACK, STAT_NEARTIE, STAT_PAIRS, STAT_LISTS, STAT_CAND = 0, 1, 2, 3, 4
+
+_METRICS = {"l2": L2, "l1": L1, L2: L2, L1: L1}
+_MODES = {"exact": EXACT, "oneshot": ONESHOT, EXACT: EXACT, ONESHOT: ONESHOT}
+_PRECS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, FP32: FP32, BF16: BF16, FP8_E4M3: FP8_E4M3}
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SZ = ctypes.c_size_t
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("precision", _I32), ("shortlist", _I32), ("splits", _I32), ("flags", _I32),
+                ("dev_stats", _P)]
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("mode", _I32), ("metric", _I32), ("n_r", _I64), ("s", _I64),
+                ("seed", ctypes.c_uint64), ("rep_idx", _P)]
+
+
+class RbcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("librbc status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librbc (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librbc.so is not built: run paper_1103_2635_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.rbc_last_error.restype = ctypes.c_char_p
+        L.bf_search_workspace_size.argtypes = [_I64, _I64, _I32, _I64, _I64, _I32, _I32, _P,
+                                               ctypes.POINTER(_SZ)]
+        L.bf_search.argtypes = [_P, _I64, _I64, _P, _I64, _I64, _I32, _I32, _I32, _P, _P, _P, _P,
+                                _SZ, _P]
+        L.rbc_build.argtypes = [_P, _I64, _I64, _I32, _P, _P, ctypes.POINTER(_P)]
+        L.rbc_search_workspace_size.argtypes = [_P, _I64, _I32, _P, ctypes.POINTER(_SZ)]
+        L.rbc_search.argtypes = [_P, _P, _I64, _I64, _I32, _P, _P, _P, _P, _SZ, _P]
+        L.rbc_index_info.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                                     ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                                     ctypes.POINTER(_I32), ctypes.POINTER(_SZ)]
+        L.rbc_index_export.argtypes = [_P, _P, _P, _P, _P]
+        L.rbc_free.argtypes = [_P]
+        L.rbc_free.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RbcError(rc, lib().rbc_last_error().decode())
+
+
+def _stream_ptr(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _mat(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.dim() != 2:
+        raise TypeError("%s must be a 2-D float32 tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be on a GPU (the library has no CPU path)" % name)
+    if t.stride(1) != 1:
+        raise ValueError("%s must have unit stride along rows" % name)
+    return t
+
+
+def _opts(precision="fp32", shortlist=0, splits=0, stats=None):
+    o = SearchOpts()
+    o.precision = _PRECS[precision]
+    o.shortlist = int(shortlist)
+    o.splits = int(splits)
+    o.flags = 0
+    if stats is not None:
+        if stats.dtype != torch.int64 or not stats.is_cuda or stats.numel() < STATS_LEN:
+            raise ValueError("stats must be a GPU int64 tensor of %d counters" % STATS_LEN)
+        o.dev_stats = stats.data_ptr()
+    return o
+
+
+def new_stats(device="cuda"):
+    """Zeroed device counters for the ``stats`` argument."""
+    return torch.zeros(STATS_LEN, dtype=torch.int64, device=device)
+
+
+def bf_search_workspace_size(m, n, d, k, metric="l2", ldq=None, ldx=None, **kw):
+    sz = _SZ()
+    o = _opts(**kw)
+    _check(lib().bf_search_workspace_size(m, n, d, ldq or d, ldx or d, _METRICS[metric], k,
+                                          ctypes.byref(o), ctypes.byref(sz)))
+    return sz.value
+
+
+def bf_search(Q, X, k, metric="l2", out=None, workspace=None, **kw):
+    """BF(Q, X): the k nearest rows of X for every row of Q.
+
+    Returns (idx int64 [m, k], dist float32 [m, k]) on Q's device, each row
+    sorted by (distance, id).  Keyword options: precision, shortlist, splits,
+    stats (see new_stats)."""
+    _mat(Q, "Q")
+    _mat(X, "X")
+    m, d = Q.shape
+    n = X.shape[0]
+    if X.shape[1] != d:
+        raise ValueError("Q and X have different dimensions")
+    o = _opts(**kw)
+    sz = _SZ()
+    _check(lib().bf_search_workspace_size(m, n, d, Q.stride(0), X.stride(0), _METRICS[metric], k,
+                                          ctypes.byref(o), ctypes.byref(sz)))
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=Q.device)
+    if out is None:
+        out = (torch.empty((m, k), dtype=torch.int64, device=Q.device),
+               torch.empty((m, k), dtype=torch.float32, device=Q.device))
+    idx, dist = out
+    _check(lib().bf_search(Q.data_ptr(), m, Q.stride(0), X.data_ptr(), n, X.stride(0), d,
+                           _METRICS[metric], k, ctypes.byref(o), idx.data_ptr(), dist.data_ptr(),
+                           workspace.data_ptr(), workspace.numel(), _stream_ptr(Q)))
+    return idx, dist
+
+
+class Index:
+    """A built Random Ball Cover (owns device memory through librbc)."""
+
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("index has been freed")
+        return self._h
+
+    def info(self):
+        n, d, n_r, mode, metric, nb = _I64(), _I32(), _I64(), _I32(), _I32(), _SZ()
+        _check(lib().rbc_index_info(self.handle, ctypes.byref(n), ctypes.byref(d),
+                                    ctypes.byref(n_r), ctypes.byref(mode), ctypes.byref(metric),
+                                    ctypes.byref(nb)))
+        return {"n": n.value, "d": d.value, "n_r": n_r.value, "mode": mode.value,
+                "metric": metric.value, "device_bytes": nb.value}
+
+    def export(self):
+        """Host copies of the index arrays (rep_idx, psi, list_off, list_ids)."""
+        import numpy as np
+
+        inf = self.info()
+        n_r = inf["n_r"]
+        rep = np.empty(n_r, np.int64)
+        psi = np.empty(n_r, np.float64)
+        off = np.empty(n_r + 1, np.int64)
+        _check(lib().rbc_index_export(self.handle, rep.ctypes.data, psi.ctypes.data,
+                                      off.ctypes.data, None))
+        ids = np.empty(int(off[-1]), np.int64)
+        _check(lib().rbc_index_export(self.handle, None, None, None, ids.ctypes.data))
+        return {"rep_idx": rep, "psi": psi, "list_off": off, "list_ids": ids}
+
+    def free(self):
+        if self._h:
+            lib().rbc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def rbc_build(X, n_r, mode="exact", metric="l2", s=0, seed=0, rep_idx=None):
+    """Build an RBC index over X (rep_idx: optional host int64 array of ids)."""
+    import numpy as np
+
+    _mat(X, "X")
+    n, d = X.shape
+    p = BuildParams()
+    p.mode = _MODES[mode]
+    p.metric = _METRICS[metric]
+    p.n_r = int(n_r)
+    p.s = int(s)
+    p.seed = int(seed)
+    reps = None
+    if rep_idx is not None:
+        reps = np.ascontiguousarray(rep_idx, dtype=np.int64)
+        if reps.shape != (int(n_r),):
+            raise ValueError("rep_idx must hold n_r ids")
+        p.rep_idx = reps.ctypes.data
+    h = _P()
+    _check(lib().rbc_build(X.data_ptr(), n, X.stride(0), d, ctypes.byref(p), _stream_ptr(X),
+                           ctypes.byref(h)))
+    return Index(h, X.device)
+
+
+def rbc_search_workspace_size(index, m, k, **kw):
+    sz = _SZ()
+    o = _opts(**kw)
+    _check(lib().rbc_search_workspace_size(index.handle, m, k, ctypes.byref(o), ctypes.byref(sz)))
+    return sz.value
+
+
+def rbc_search(index, Q, k, out=None, workspace=None, **kw):
+    """Search an RBC index; returns (idx int64 [m, k], dist float32 [m, k])."""
+    _mat(Q, "Q")
+    m = Q.shape[0]
+    o = _opts(**kw)
+    sz = _SZ()
+    _check(lib().rbc_search_workspace_size(index.handle, m, k, ctypes.byref(o), ctypes.byref(sz)))
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=Q.device)
+    if out is None:
+        out = (torch.empty((m, k), dtype=torch.int64, device=Q.device),
+               torch.empty((m, k), dtype=torch.float32, device=Q.device))
+    idx, dist = out
+    _check(lib().rbc_search(index.handle, Q.data_ptr(), m, Q.stride(0), k, ctypes.byref(o),
+                            idx.data_ptr(), dist.data_ptr(), workspace.data_ptr(),
+                            workspace.numel(), _stream_ptr(Q)))
+    return idx, dist

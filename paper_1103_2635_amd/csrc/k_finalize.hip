@@ -1,0 +1,288 @@
+// k_finalize.hip -- the end of the comparison step: merge the partial
+// shortlists of all database splits, re-score the shortlist directly, re-rank
+// near-ties in float64, certify the shortlist, write the k results.  Queries
+// that cannot be certified are listed for an exhaustive float64 search
+// (exact_fp64 below), which is also the path for k or d beyond the tiles.
+//
+// Certificate.  Every row outside the merged shortlist had a tile value at
+// least A_c (the shortlist's c-th value).  With a rigorous bound on the tile's
+// rounding error this gives a lower bound on the true distance of any row
+// outside the shortlist; if it is strictly above the k-th re-scored distance
+// (widened by that value's own error), the k best rows are all inside the
+// shortlist.  Error bounds, with u = 2^-24:
+//   matrix-core tile (values ||x||^2 - 2 q.x, ||q||^2 added here):
+//       |error of d^2| <= 4 (d + 2) u (||q|| + max ||x||)^2
+//   direct fp32 (d^2 or l1 sum of non-negative terms): relative 2 (d + 2) u.
+// The factor 4 (resp. 2) is a safety margin over the textbook bound of a
+// d-term dot product, for any summation order.
+#include "rbc_device.h"
+
+namespace rbc {
+
+#define RBC_INF_D __builtin_huge_val()
+
+// Float64 distance in a fixed order: differences of the exactly converted
+// inputs, summed from the first feature to the last, no fused multiply-add.
+__device__ __noinline__ double rho_fp64(const float* a, const float* b, int d, int metric) {
+#pragma clang fp contract(off)
+    double s = 0.0;
+    if (metric == 1) {
+        for (int i = 0; i < d; ++i) s += __builtin_fabs((double)a[i] - (double)b[i]);
+        return s;
+    }
+    for (int i = 0; i < d; ++i) {
+        const double t = (double)a[i] - (double)b[i];
+        s += t * t;
+    }
+    return __builtin_sqrt(s);
+}
+
+__device__ __forceinline__ bool before(double va, int64_t ia, double vb, int64_t ib) {
+    return va < vb || (va == vb && ia < ib);
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (slot >= a.m) return;  // uniform per wavefront
+    const int qrow = a.qmap ? a.qmap[slot] : slot;
+    const int64_t stride = (int64_t)a.m * C;
+
+    // 1. merge the sorted partial lists (lane s < nsplit reads list s)
+    float mv = RBC_INF;
+    int32_t mi = -1;
+    if (a.nsplit == 1) {
+        if (lane < C) {
+            mv = a.pval[(int64_t)slot * C + lane];
+            mi = a.pidx[(int64_t)slot * C + lane];
+        }
+    } else {
+        int ptr = 0;
+        float hv = RBC_INF;
+        int32_t hi = 0x7fffffff;
+        const float* lv = a.pval + (int64_t)lane * stride + (int64_t)slot * C;
+        const int32_t* li = a.pidx + (int64_t)lane * stride + (int64_t)slot * C;
+        if (lane < a.nsplit) {
+            hv = lv[0];
+            hi = li[0];
+        }
+        for (int r = 0; r < C; ++r) {
+            float bv = hv;
+            int32_t bi = hi;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const float ov = __shfl_xor(bv, off);
+                const int32_t oi = __shfl_xor(bi, off);
+                if (ov < bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            if (lane == r) {
+                mv = bv;
+                mi = bi;
+            }
+            if (lane < a.nsplit && hv == bv && hi == bi) {
+                ++ptr;
+                if (ptr < C) {
+                    hv = lv[ptr];
+                    hi = li[ptr];
+                } else {
+                    hv = RBC_INF;
+                    hi = 0x7fffffff;
+                }
+            }
+        }
+    }
+    const bool valid = lane < C && mi >= 0 && mv < RBC_INF;
+    const float a_c = __shfl(mv, C - 1);
+
+    // 2. direct re-score in fp32
+    const float* qp = a.Q + (int64_t)qrow * a.ldq;
+    const float* xp = a.X + (int64_t)(valid ? mi : 0) * a.ldx;
+    double rho = RBC_INF_D;
+    if (valid) {
+        float s = 0.f;
+        if (a.metric == 0) {
+            for (int f = 0; f < a.d; ++f) {
+                const float t = qp[f] - xp[f];
+                s = __builtin_fmaf(t, t, s);
+            }
+            rho = __builtin_sqrt((double)s);
+        } else {
+            for (int f = 0; f < a.d; ++f) s += __builtin_fabsf(qp[f] - xp[f]);
+            rho = (double)s;
+        }
+    }
+
+    // 3. float64 re-rank of near-ties
+    const double u = 5.9604644775390625e-8;
+    const double delta = 2.0 * (a.d + 2) * u;  // relative error of a direct fp32 distance
+    const double tol = 2.0 * delta;
+    bool flag = false;
+    for (int i = 0; i < C; ++i) {
+        const double ri = __shfl(rho, i);
+        if (i != lane && valid && ri < RBC_INF_D &&
+            __builtin_fabs(ri - rho) <= tol * (ri > rho ? ri : rho))
+            flag = true;
+    }
+    if (flag) rho = rho_fp64(qp, xp, a.d, a.metric);
+    const uint64_t flagged = __ballot(flag);
+
+    // 4. rank by (distance, reported id)
+    const int64_t myid = valid ? (a.id_map ? a.id_map[mi] : (int64_t)mi) : INT64_MAX;
+    int rank = 0;
+    for (int i = 0; i < C; ++i) {
+        const double ri = __shfl(rho, i);
+        const int64_t ii = __shfl(myid, i);
+        if (i != lane && before(ri, ii, rho, myid)) ++rank;
+    }
+    const int nvalid = __popcll(__ballot(valid));
+
+    // 5. certificate
+    bool ok = nvalid >= a.k;
+    if (ok && a_c < RBC_INF) {
+        const uint64_t kth = __ballot(valid && rank == a.k - 1);
+        const double t_k = __shfl(rho, (int)__builtin_ctzll(kth));
+        double lo;
+        if (a.approx_mode == 0) {
+            const double qn = a.qn[slot];
+            const double xmax = (double)__uint_as_float(*a.xmax_bits);
+            const double sq = __builtin_sqrt(qn) + xmax;
+            const double e = 4.0 * (a.d + 2) * u * sq * sq;
+            const double lo2 = (double)a_c + qn - e;
+            lo = lo2 > 0.0 ? __builtin_sqrt(lo2) : 0.0;
+        } else if (a.metric == 0) {
+            lo = __builtin_sqrt((double)a_c) * (1.0 - delta);
+        } else {
+            lo = (double)a_c * (1.0 - delta);
+        }
+        ok = lo > t_k * (1.0 + delta);
+    }
+
+    if (!ok) {
+        if (lane == 0) {
+            const int p = atomicAdd(a.fb_count, 1);
+            a.fb_list[p] = qrow;
+        }
+    } else if (valid && rank < a.k) {
+        a.out_idx[(int64_t)qrow * a.k + rank] = myid;
+        a.out_dist[(int64_t)qrow * a.k + rank] = (float)rho;
+    }
+    if (a.stats && lane == 0) {
+        if (!ok) atomicAdd((unsigned long long*)&a.stats[0], 1ull);
+        if (flagged) atomicAdd((unsigned long long*)&a.stats[1], (unsigned long long)__popcll(flagged));
+    }
+}
+
+hipError_t launch_finalize(int c, const FinArgs& a, hipStream_t st) {
+    const dim3 grid((a.m + 3) / 4);
+    switch (c) {
+        case 4: hipLaunchKernelGGL((finalize_kernel<4>), grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((finalize_kernel<8>), grid, dim3(256), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((finalize_kernel<16>), grid, dim3(256), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((finalize_kernel<32>), grid, dim3(256), 0, st, a); break;
+        case 64: hipLaunchKernelGGL((finalize_kernel<64>), grid, dim3(256), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exhaustive float64 search (any k <= kExactKCap) for the listed queries: one
+// workgroup per query, rows scored one per thread in float64 (the fixed order
+// of rho_fp64), candidates below the current k-th value appended to an LDS
+// buffer, buffer and current top-k merged by rank counting when it fills.
+constexpr int kExactBuf = 1024;
+
+__global__ __launch_bounds__(256) void exact_fp64_kernel(ExactArgs a) {
+    __shared__ double tv[kExactKCap];
+    __shared__ int64_t ti[kExactKCap];
+    __shared__ double bv[kExactBuf];
+    __shared__ int64_t bi[kExactBuf];
+    __shared__ int s_kcnt, s_bcnt;
+    __shared__ double s_thr;
+    __shared__ int64_t s_thr_id;
+    const int tid = threadIdx.x;
+    const int count = *a.count;
+
+    for (int f = blockIdx.x; f < count; f += gridDim.x) {
+        const int qrow = a.list[f];
+        const float* qp = a.Q + (int64_t)qrow * a.ldq;
+        if (tid == 0) {
+            s_kcnt = 0;
+            s_bcnt = 0;
+            s_thr = RBC_INF_D;
+            s_thr_id = INT64_MAX;
+        }
+        __syncthreads();
+        for (int base = 0; base < a.n; base += 256) {
+            const int row = base + tid;
+            if (row < a.n) {
+                const double r = rho_fp64(qp, a.X + (int64_t)row * a.ldx, a.d, a.metric);
+                const int64_t id = a.id_map ? a.id_map[row] : (int64_t)row;
+                if (before(r, id, s_thr, s_thr_id)) {
+                    const int p = atomicAdd(&s_bcnt, 1);
+                    bv[p] = r;
+                    bi[p] = id;
+                }
+            }
+            __syncthreads();
+            const int bcnt = s_bcnt;
+            if (bcnt > kExactBuf - 256 || base + 256 >= a.n) {
+                // merge: rank every entry of (top, buffer) by counting the
+                // entries before it; ranks are distinct, keep ranks < k.
+                const int kcnt = s_kcnt;
+                const int tot = kcnt + bcnt;
+                double myv[8];
+                int64_t myi[8];
+                int myr[8];
+                int nmine = 0;
+                for (int e = tid; e < tot; e += 256) {
+                    const double v = e < kcnt ? tv[e] : bv[e - kcnt];
+                    const int64_t id = e < kcnt ? ti[e] : bi[e - kcnt];
+                    int rk = 0;
+                    for (int j = 0; j < tot; ++j) {
+                        const double vj = j < kcnt ? tv[j] : bv[j - kcnt];
+                        const int64_t ij = j < kcnt ? ti[j] : bi[j - kcnt];
+                        rk += before(vj, ij, v, id) ? 1 : 0;
+                    }
+                    myv[nmine] = v;
+                    myi[nmine] = id;
+                    myr[nmine] = rk;
+                    ++nmine;
+                }
+                __syncthreads();
+                for (int t = 0; t < nmine; ++t) {
+                    if (myr[t] < a.k) {
+                        tv[myr[t]] = myv[t];
+                        ti[myr[t]] = myi[t];
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    const int nk = tot < a.k ? tot : a.k;
+                    s_kcnt = nk;
+                    s_bcnt = 0;
+                    s_thr = nk == a.k ? tv[nk - 1] : RBC_INF_D;
+                    s_thr_id = nk == a.k ? ti[nk - 1] : INT64_MAX;
+                }
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < a.k; e += 256) {
+            const bool have = e < s_kcnt;
+            a.out_idx[(int64_t)qrow * a.k + e] = have ? ti[e] : -1;
+            a.out_dist[(int64_t)qrow * a.k + e] = have ? (float)tv[e] : RBC_INF;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_exact(const ExactArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(exact_fp64_kernel, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace rbc

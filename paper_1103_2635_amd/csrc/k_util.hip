@@ -1,0 +1,96 @@
+// k_util.hip -- small kernels: fills, row repacking, row norms.
+#include "rbc_device.h"
+
+namespace rbc {
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t count, int32_t value) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, count, value);
+    return hipGetLastError();
+}
+
+__global__ void iota_i32_kernel(int32_t* p, int32_t count) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = i;
+}
+
+hipError_t launch_iota_i32(int32_t* p, int32_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_i32_kernel, dim3((count + 255) / 256), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+__global__ void set_count_kernel(int32_t* p, int32_t value) { *p = value; }
+
+hipError_t launch_set_count(int32_t* p, int32_t value, hipStream_t st) {
+    hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(1), 0, st, p, value);
+    return hipGetLastError();
+}
+
+// out[r][0 .. ldo) = A[r][0 .. d) followed by zeros.
+__global__ void repack_kernel(const float* A, int64_t rows, int64_t lda, int32_t d, float* out,
+                              int64_t ldo) {
+    const int64_t total = rows * ldo;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / ldo;
+        const int64_t c = e - r * ldo;
+        out[e] = c < d ? A[r * lda + c] : 0.f;
+    }
+}
+
+hipError_t launch_repack(const float* A, int64_t rows, int64_t lda, int32_t d, float* out,
+                         int64_t ldo, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    int64_t blocks = (rows * ldo + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(repack_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, rows, lda, d,
+                       out, ldo);
+    return hipGetLastError();
+}
+
+// Squared norm of every row (16 lanes per row, fp32), and the largest row norm
+// as float bits through an integer atomic max (valid for non-negative floats).
+// rowmap (optional) gives the source row of output row i.
+__global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t rows, int64_t lda,
+                                                        int32_t d, const int32_t* rowmap,
+                                                        float* out, uint32_t* maxbits) {
+    const int sub = threadIdx.x & 15;
+    const int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    float s = 0.f;
+    if (r < rows) {
+        const int64_t src = rowmap ? rowmap[r] : r;
+        const float* p = A + src * lda;
+        for (int f = sub; f < d; f += 16) s = __builtin_fmaf(p[f], p[f], s);
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (r < rows && sub == 0) out[r] = s;
+    if (maxbits) {
+        float nv = r < rows ? __builtin_sqrtf(s) : 0.f;
+#pragma unroll
+        for (int off = 32; off >= 16; off >>= 1) nv = fmaxf(nv, __shfl_xor(nv, off));
+        // lanes 0..15 of each wavefront now hold the wavefront max
+        if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(nv));
+    }
+}
+
+hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d,
+                            const int32_t* rowmap, float* out, uint32_t* maxbits,
+                            hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    const int64_t blocks = (rows * 16 + 255) / 256;
+    hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, rows, lda,
+                       d, rowmap, out, maxbits);
+    return hipGetLastError();
+}
+
+}  // namespace rbc

@@ -1,0 +1,291 @@
+// rbc_api.cpp -- the C ABI of librbc (declared in include/rbc.h): argument
+// validation, plans (path, shortlist length, database splits), workspace
+// carving and the launch sequence of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/rbc.h"
+#include "rbc_common.h"
+#include "rbc_host.h"
+
+namespace rbc {
+
+static thread_local char g_err[512] = "";
+
+int set_err(int status, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+const char* last_error() { return g_err; }
+
+int hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return RBC_OK;
+    return set_err(RBC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int shortlist_len(int k, int requested) {
+    int want = k + 3;
+    if (requested > want) want = requested;
+    for (int c : {4, 8, 16, 32, 64})
+        if (c >= want) return c;
+    return 0;  // beyond the register shortlist: exhaustive float64 path
+}
+
+// ---------------------------------------------------------------- BF plan
+
+int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int32_t metric,
+                 int32_t k, const rbc_search_opts* opts, BfPlan* p) {
+    std::memset(p, 0, sizeof(*p));
+    const int prec = opts ? opts->precision : RBC_FP32;
+    if (prec != RBC_FP32)
+        return set_err(RBC_EUNSUPPORTED, "precision %d is not implemented (only RBC_FP32)", prec);
+    if (opts && opts->flags != 0) return set_err(RBC_EINVAL, "opts->flags must be 0");
+    p->metric = metric;
+    p->k = k;
+    p->d = d;
+    p->ldp = ((int64_t)d + 3) / 4 * 4;
+    p->repack_q = (d % 4) != 0 || (ldq % 4) != 0;
+    p->repack_x = (d % 4) != 0 || (ldx % 4) != 0;
+    p->c = shortlist_len(k, opts ? opts->shortlist : 0);
+    p->ks = (d + 15) / 16;
+    if (p->c == 0 || p->ks > kMaxKS) {
+        p->path = kPathExact;
+        p->c = 0;
+        p->ks = 0;
+        p->repack_q = p->repack_x = false;
+    } else if (metric == RBC_L2 && d >= 12) {
+        p->path = kPathMfma;
+    } else {
+        p->path = kPathValu;
+    }
+    p->nqblk = (int32_t)((m + kTileQ - 1) / kTileQ);
+    if (p->path != kPathExact) {
+        int64_t s = opts && opts->splits > 0 ? opts->splits : (4 * kConcurrentBlocks) / p->nqblk;
+        s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
+        s = std::min<int64_t>(s, (n + 255) / 256);
+        s = std::max<int64_t>(s, 1);
+        int64_t rps = (n + s - 1) / s;
+        rps = (rps + kRowsMfma - 1) / kRowsMfma * kRowsMfma;
+        p->rps = (int32_t)rps;
+        p->nsplit = (int32_t)((n + rps - 1) / rps);
+    }
+    return RBC_OK;
+}
+
+void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
+    w->fb_list = cv.take<int32_t>(m);
+    w->counters = cv.take<int32_t>(4);
+    if (p.path == kPathExact) return;
+    if (p.repack_q) w->Qp = cv.take<float>(m * p.ldp);
+    if (p.repack_x) w->Xp = cv.take<float>(n * p.ldp);
+    if (p.path == kPathMfma) {
+        w->qn = cv.take<float>(m);
+        w->xn = cv.take<float>(n);
+    }
+    w->pval = cv.take<float>((int64_t)p.nsplit * m * p.c);
+    w->pidx = cv.take<int32_t>((int64_t)p.nsplit * m * p.c);
+}
+
+// The launch sequence shared by bf_search and the RBC paths: tile over the
+// database rows (BF mode or grouped mode), finalize, exhaustive fallback.
+int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_t* qmap,
+           const float* X, int64_t n, int64_t ldx, const float* xn, const uint32_t* xmax_bits,
+           const int64_t* id_map, const GroupedArgs* grp, int64_t* out_idx, float* out_dist,
+           BfWork& w, int64_t* stats, hipStream_t st) {
+    int32_t* fb_count = w.counters;
+    if (p.path == kPathExact) {
+        if (qmap) return set_err(RBC_EUNSUPPORTED, "exhaustive path with a query map");
+        int rc = hip_status(launch_iota_i32(w.fb_list, (int32_t)m, st), "iota");
+        if (rc) return rc;
+        rc = hip_status(launch_set_count(fb_count, (int32_t)m, st), "set_count");
+        if (rc) return rc;
+    } else {
+        const float* Qk = Q;
+        int64_t ldqk = ldq;
+        const float* Xk = X;
+        int64_t ldxk = ldx;
+        int rc;
+        if (p.repack_q) {
+            rc = hip_status(launch_repack(Q, m, ldq, p.d, w.Qp, p.ldp, st), "repack Q");
+            if (rc) return rc;
+            Qk = w.Qp;
+            ldqk = p.ldp;
+        }
+        if (p.repack_x) {
+            rc = hip_status(launch_repack(X, n, ldx, p.d, w.Xp, p.ldp, st), "repack X");
+            if (rc) return rc;
+            Xk = w.Xp;
+            ldxk = p.ldp;
+        }
+        rc = hip_status(launch_fill_i32(w.counters, 4, 0, st), "clear counters");
+        if (rc) return rc;
+        const uint32_t* xmaxp = xmax_bits;
+        if (p.path == kPathMfma) {
+            rc = hip_status(launch_row_norms(Qk, m, ldqk, p.d, qmap, w.qn, nullptr, st), "norms Q");
+            if (rc) return rc;
+            if (xn == nullptr) {
+                uint32_t* xm = (uint32_t*)(w.counters + 1);
+                rc = hip_status(launch_row_norms(Xk, n, ldxk, p.d, nullptr, w.xn, xm, st), "norms X");
+                if (rc) return rc;
+                xn = w.xn;
+                xmaxp = xm;
+            }
+        }
+        TileArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.Q = Qk;
+        a.ldq = ldqk;
+        a.m = (int32_t)m;
+        a.qmap = qmap;
+        a.X = Xk;
+        a.ldx = ldxk;
+        a.n = (int32_t)n;
+        a.d = p.d;
+        a.xn = xn;
+        a.rps = p.rps;
+        a.nsplit = p.nsplit;
+        if (grp) {
+            a.blk_reps = grp->blk_reps;
+            a.blk_cnt = grp->blk_cnt;
+            a.blk_pre = grp->blk_pre;
+            a.list_off = grp->list_off;
+            a.keep = grp->keep;
+            a.n_r = grp->n_r;
+        }
+        a.pval = w.pval;
+        a.pidx = w.pidx;
+        a.stats = stats;
+        const dim3 grid(p.nqblk, p.nsplit);
+        if (p.path == kPathMfma)
+            rc = hip_status(launch_tile_mfma(p.ks, p.c, grp != nullptr, grid, a, st), "tile (mfma)");
+        else
+            rc = hip_status(launch_tile_valu(p.metric, p.ks, p.c, grp != nullptr, grid, a, st),
+                            "tile (valu)");
+        if (rc) return rc;
+
+        FinArgs f;
+        std::memset(&f, 0, sizeof(f));
+        f.Q = Qk;
+        f.ldq = ldqk;
+        f.m = (int32_t)m;
+        f.qmap = qmap;
+        f.X = Xk;
+        f.ldx = ldxk;
+        f.d = p.d;
+        f.metric = p.metric;
+        f.approx_mode = p.path == kPathMfma ? 0 : 1;
+        f.pval = w.pval;
+        f.pidx = w.pidx;
+        f.nsplit = p.nsplit;
+        f.k = p.k;
+        f.qn = w.qn;
+        f.xmax_bits = xmaxp;
+        f.id_map = id_map;
+        f.out_idx = out_idx;
+        f.out_dist = out_dist;
+        f.fb_list = w.fb_list;
+        f.fb_count = fb_count;
+        f.stats = stats;
+        rc = hip_status(launch_finalize(p.c, f, st), "finalize");
+        if (rc) return rc;
+    }
+    ExactArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.Q = Q;
+    e.ldq = ldq;
+    e.X = X;
+    e.ldx = ldx;
+    e.n = (int32_t)n;
+    e.d = p.d;
+    e.metric = p.metric;
+    e.k = p.k;
+    e.list = w.fb_list;
+    e.count = fb_count;
+    e.id_map = id_map;
+    e.out_idx = out_idx;
+    e.out_dist = out_dist;
+    int grid = p.path == kPathExact ? (int)std::min<int64_t>(m, 2048) : kFallbackBlocks;
+    return hip_status(launch_exact(e, grid, st), "exact fallback");
+}
+
+int validate_common(int64_t m, int64_t n, int32_t d, int32_t k, int32_t metric) {
+    if (d < 1) return set_err(RBC_EINVAL, "d must be >= 1 (got %d)", d);
+    if (n < 1) return set_err(RBC_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+    if (m < 0) return set_err(RBC_EINVAL, "m must be >= 0 (got %lld)", (long long)m);
+    if (k < 1) return set_err(RBC_EINVAL, "k must be >= 1 (got %d)", k);
+    if (k > n) return set_err(RBC_EINVAL, "k (%d) exceeds the database size (%lld)", k, (long long)n);
+    if (metric != RBC_L2 && metric != RBC_L1) return set_err(RBC_EINVAL, "unknown metric %d", metric);
+    if (d > RBC_MAX_D) return set_err(RBC_EUNSUPPORTED, "d > %d", RBC_MAX_D);
+    if (k > RBC_MAX_K) return set_err(RBC_EUNSUPPORTED, "k > %d", RBC_MAX_K);
+    if (n >= (int64_t)1 << 31) return set_err(RBC_EUNSUPPORTED, "n >= 2^31");
+    if (m >= (int64_t)1 << 31) return set_err(RBC_EUNSUPPORTED, "m >= 2^31");
+    return RBC_OK;
+}
+
+}  // namespace rbc
+
+using namespace rbc;
+
+extern "C" {
+
+const char* rbc_last_error(void) { return last_error(); }
+
+int bf_search_workspace_size(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx,
+                             int32_t metric, int32_t k, const rbc_search_opts* opts,
+                             size_t* bytes) {
+    try {
+        if (!bytes) return set_err(RBC_EINVAL, "bytes is NULL");
+        int rc = validate_common(m, n, d, k, metric);
+        if (rc) return rc;
+        if (ldq < d || ldx < d) return set_err(RBC_EINVAL, "leading dimension smaller than d");
+        BfPlan p;
+        rc = make_bf_plan(m > 0 ? m : 1, n, d, ldq, ldx, metric, k, opts, &p);
+        if (rc) return rc;
+        Carver cv(nullptr);
+        BfWork w;
+        carve_bf(p, m, n, cv, &w);
+        *bytes = cv.size();
+        return RBC_OK;
+    } catch (...) {
+        return set_err(RBC_EHIP, "unexpected exception");
+    }
+}
+
+int bf_search(const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n, int64_t ldx,
+              int32_t d, int32_t metric, int32_t k, const rbc_search_opts* opts, int64_t* out_idx,
+              float* out_dist, void* workspace, size_t ws_bytes, void* hip_stream) {
+    try {
+        int rc = validate_common(m, n, d, k, metric);
+        if (rc) return rc;
+        if (ldq < d || ldx < d) return set_err(RBC_EINVAL, "leading dimension smaller than d");
+        if (m == 0) return RBC_OK;
+        if (!Q || !X || !out_idx || !out_dist) return set_err(RBC_EINVAL, "NULL pointer");
+        if (((uintptr_t)Q | (uintptr_t)X) & 15)
+            return set_err(RBC_EINVAL, "Q and X must be 16-byte aligned");
+        BfPlan p;
+        rc = make_bf_plan(m, n, d, ldq, ldx, metric, k, opts, &p);
+        if (rc) return rc;
+        Carver cv((char*)workspace);
+        BfWork w;
+        carve_bf(p, m, n, cv, &w);
+        if (!workspace || ws_bytes < cv.size())
+            return set_err(RBC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu needed",
+                           ws_bytes, cv.size());
+        return run_bf(p, Q, m, ldq, nullptr, X, n, ldx, nullptr, nullptr, nullptr, nullptr,
+                      out_idx, out_dist, w, opts ? opts->dev_stats : nullptr,
+                      (hipStream_t)hip_stream);
+    } catch (...) {
+        return set_err(RBC_EHIP, "unexpected exception");
+    }
+}
+
+}  // extern "C"

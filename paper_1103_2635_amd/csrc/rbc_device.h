@@ -1,0 +1,101 @@
+// rbc_device.h -- device helpers shared by the tile kernels: the per-query
+// shortlist (the comparison step of BF, Sec. 3, kept as a sorted top-c list in
+// registers) and the walk over the rows a workgroup has to scan.
+#pragma once
+
+#include "rbc_common.h"
+
+namespace rbc {
+
+#define RBC_INF __builtin_huge_valf()
+
+// Sorted ascending top-C list held by one lane.  Values arrive in increasing
+// row order, so the strict comparison keeps the earlier (lower) row on a tie.
+template <int C>
+struct TopC {
+    float v[C];
+    int32_t i[C];
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            v[j] = RBC_INF;
+            i[j] = -1;
+        }
+    }
+
+    __device__ __forceinline__ float worst() const { return v[C - 1]; }
+
+    // Insert (x, id) given x < v[C - 1]; the last entry drops out.
+    __device__ __forceinline__ void insert(float x, int32_t id) {
+        bool lt[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) lt[j] = x < v[j];
+#pragma unroll
+        for (int j = C - 1; j > 0; --j) {
+            const float nv = lt[j - 1] ? v[j - 1] : (lt[j] ? x : v[j]);
+            const int32_t ni = lt[j - 1] ? i[j - 1] : (lt[j] ? id : i[j]);
+            v[j] = nv;
+            i[j] = ni;
+        }
+        v[0] = lt[0] ? x : v[0];
+        i[0] = lt[0] ? id : i[0];
+    }
+
+    __device__ __forceinline__ void push(float x, int32_t id) {
+        if (x < v[C - 1]) insert(x, id);
+    }
+
+    __device__ __forceinline__ void store(float* pv, int32_t* pi) const {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            pv[j] = v[j];
+            pi[j] = i[j];
+        }
+    }
+};
+
+// Calls body(r0, r1, rep) for every row range this (query block, split)
+// workgroup scans.  rep = -1 in BF mode.  Uniform across the workgroup.
+template <typename Body>
+__device__ __forceinline__ void for_each_segment(const TileArgs& a, int qblk, int split,
+                                                 Body&& body) {
+    if (a.blk_reps == nullptr) {
+        const int64_t r0 = (int64_t)split * a.rps;
+        const int64_t r1 = r0 + a.rps < a.n ? r0 + a.rps : a.n;
+        if (r0 < r1) body((int32_t)r0, (int32_t)r1, -1);
+        return;
+    }
+    const int32_t cnt = a.blk_cnt[qblk];
+    const int64_t* pre = a.blk_pre + (int64_t)qblk * (a.n_r + 1);
+    const int32_t* reps = a.blk_reps + (int64_t)qblk * a.n_r;
+    const int64_t total = pre[cnt];
+    const int64_t start = total * split / a.nsplit;
+    const int64_t end = total * (split + 1) / a.nsplit;
+    if (start >= end) return;
+    // first j with pre[j + 1] > start
+    int32_t lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (pre[mid + 1] > start) hi = mid; else lo = mid + 1;
+    }
+    for (int32_t j = lo; j < cnt && pre[j] < end; ++j) {
+        const int32_t r = reps[j];
+        const int64_t a0 = start > pre[j] ? start : pre[j];
+        const int64_t a1 = end < pre[j + 1] ? end : pre[j + 1];
+        if (a0 >= a1) continue;
+        const int32_t base = a.list_off[r];
+        body(base + (int32_t)(a0 - pre[j]), base + (int32_t)(a1 - pre[j]), r);
+    }
+}
+
+// Makes this wavefront's LDS writes visible to its own later LDS reads (and
+// keeps the compiler from moving LDS accesses across the point).  LDS
+// operations of one wavefront are executed in issue order.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace rbc

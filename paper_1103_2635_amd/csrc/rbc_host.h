@@ -1,0 +1,86 @@
+// rbc_host.h -- host-side plan and workspace types of librbc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rbc.h"
+#include "rbc_common.h"
+
+namespace rbc {
+
+constexpr int kPathMfma = 0;   // L2 tile on the matrix cores
+constexpr int kPathValu = 1;   // l1 / small-d l2 tile on the vector ALUs
+constexpr int kPathExact = 2;  // exhaustive float64 (k or d beyond the tiles)
+constexpr int kConcurrentBlocks = 512;  // 256 CUs x 2 resident tile workgroups
+constexpr int kMaxSplits = 64;          // one partial list per lane in finalize
+constexpr int kFallbackBlocks = 256;
+
+int set_err(int status, const char* fmt, ...);
+const char* last_error();
+int hip_status(hipError_t e, const char* what);
+int shortlist_len(int k, int requested);
+
+// Bump allocator over a caller-provided workspace (base == nullptr: size only).
+class Carver {
+public:
+    explicit Carver(char* base) : base_(base), off_(0) {}
+    template <class T>
+    T* take(int64_t count) {
+        off_ = (off_ + 255) / 256 * 256;
+        T* p = base_ ? (T*)(base_ + off_) : nullptr;
+        off_ += (size_t)(count > 0 ? count : 0) * sizeof(T);
+        return p;
+    }
+    size_t size() const { return (off_ + 255) / 256 * 256; }
+
+private:
+    char* base_;
+    size_t off_;
+};
+
+struct BfPlan {
+    int path;
+    int metric;
+    int k;
+    int d;
+    int64_t ldp;       // leading dimension of repacked copies (d rounded up to 4)
+    bool repack_q, repack_x;
+    int c;             // shortlist length
+    int ks;            // 16-feature slabs
+    int32_t nqblk;     // 256-query blocks
+    int32_t nsplit;    // database splits
+    int32_t rps;       // rows per split (BF mode)
+};
+
+struct BfWork {
+    int32_t* fb_list = nullptr;
+    int32_t* counters = nullptr;  // [0] fallback count, [1] max row norm bits
+    float* Qp = nullptr;
+    float* Xp = nullptr;
+    float* qn = nullptr;
+    float* xn = nullptr;
+    float* pval = nullptr;
+    int32_t* pidx = nullptr;
+};
+
+struct GroupedArgs {
+    const int32_t* blk_reps;
+    const int32_t* blk_cnt;
+    const int64_t* blk_pre;
+    const int32_t* list_off;
+    const uint8_t* keep;
+    int32_t n_r;
+};
+
+int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int32_t metric,
+                 int32_t k, const rbc_search_opts* opts, BfPlan* p);
+void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w);
+int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_t* qmap,
+           const float* X, int64_t n, int64_t ldx, const float* xn, const uint32_t* xmax_bits,
+           const int64_t* id_map, const GroupedArgs* grp, int64_t* out_idx, float* out_dist,
+           BfWork& w, int64_t* stats, hipStream_t st);
+int validate_common(int64_t m, int64_t n, int32_t d, int32_t k, int32_t metric);
+
+}  // namespace rbc
