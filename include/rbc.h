@@ -156,7 +156,7 @@ int rbc_build(const float* X, int64_t n, int64_t ldx, int32_t d,
  *   different streams with different workspaces are safe (the index is
  *   read-only after rbc_build).
  */
-int rbc_search_workspace_size(const rbc_index* index, int64_t m, int32_t k,
+int rbc_search_workspace_size(const rbc_index* index, int64_t m, int64_t ldq, int32_t k,
                               const rbc_search_opts* opts, size_t* bytes);
 int rbc_search(const rbc_index* index, const float* Q, int64_t m, int64_t ldq, int32_t k,
                const rbc_search_opts* opts, int64_t* out_idx, float* out_dist,

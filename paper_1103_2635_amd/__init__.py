@@ -64,7 +64,7 @@ def lib():
         L.bf_search.argtypes = [_P, _I64, _I64, _P, _I64, _I64, _I32, _I32, _I32, _P, _P, _P, _P,
                                 _SZ, _P]
         L.rbc_build.argtypes = [_P, _I64, _I64, _I32, _P, _P, ctypes.POINTER(_P)]
-        L.rbc_search_workspace_size.argtypes = [_P, _I64, _I32, _P, ctypes.POINTER(_SZ)]
+        L.rbc_search_workspace_size.argtypes = [_P, _I64, _I64, _I32, _P, ctypes.POINTER(_SZ)]
         L.rbc_search.argtypes = [_P, _P, _I64, _I64, _I32, _P, _P, _P, _P, _SZ, _P]
         L.rbc_index_info.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_I64), ctypes.POINTER(_I32),
@@ -221,10 +221,11 @@ def rbc_build(X, n_r, mode="exact", metric="l2", s=0, seed=0, rep_idx=None):
     return Index(h, X.device)
 
 
-def rbc_search_workspace_size(index, m, k, **kw):
+def rbc_search_workspace_size(index, m, k, ldq=None, **kw):
     sz = _SZ()
     o = _opts(**kw)
-    _check(lib().rbc_search_workspace_size(index.handle, m, k, ctypes.byref(o), ctypes.byref(sz)))
+    _check(lib().rbc_search_workspace_size(index.handle, m, ldq or index.info()["d"], k,
+                                           ctypes.byref(o), ctypes.byref(sz)))
     return sz.value
 
 
@@ -234,7 +235,8 @@ def rbc_search(index, Q, k, out=None, workspace=None, **kw):
     m = Q.shape[0]
     o = _opts(**kw)
     sz = _SZ()
-    _check(lib().rbc_search_workspace_size(index.handle, m, k, ctypes.byref(o), ctypes.byref(sz)))
+    _check(lib().rbc_search_workspace_size(index.handle, m, Q.stride(0), k, ctypes.byref(o),
+                                           ctypes.byref(sz)))
     if workspace is None or workspace.numel() < sz.value:
         workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=Q.device)
     if out is None:

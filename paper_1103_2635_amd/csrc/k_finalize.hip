@@ -19,28 +19,6 @@
 
 namespace rbc {
 
-#define RBC_INF_D __builtin_huge_val()
-
-// Float64 distance in a fixed order: differences of the exactly converted
-// inputs, summed from the first feature to the last, no fused multiply-add.
-__device__ __noinline__ double rho_fp64(const float* a, const float* b, int d, int metric) {
-#pragma clang fp contract(off)
-    double s = 0.0;
-    if (metric == 1) {
-        for (int i = 0; i < d; ++i) s += __builtin_fabs((double)a[i] - (double)b[i]);
-        return s;
-    }
-    for (int i = 0; i < d; ++i) {
-        const double t = (double)a[i] - (double)b[i];
-        s += t * t;
-    }
-    return __builtin_sqrt(s);
-}
-
-__device__ __forceinline__ bool before(double va, int64_t ia, double vb, int64_t ib) {
-    return va < vb || (va == vb && ia < ib);
-}
-
 template <int C>
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     const int lane = threadIdx.x & 63;
