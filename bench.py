@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Exact k-NN throughput of the Random Ball Cover hot path on one MI355X.
+
+Workload: n=1,000,000 database points, d=64, on a random 8-dim linear
+subspace (N(0,1) coordinates, random orthonormal embedding) plus N(0, 0.01^2)
+noise; m=10,000 queries from the same generator; n_r=1,000 representatives
+drawn uniformly (seeded); Euclidean metric, k=1.  All data synthetic, seeded.
+
+One step = the whole exact-RBC job on one batch, inputs resident in HBM:
+rbc_build (BF(X, R) ownership, counting sort, radii) + rbc_search of the
+10,000 queries (stage 1, pruning, grouping, grouped stage-2 tile, shortlist
+re-score and certificate).  `value` = queries per second of that step.
+Also reported: search-only throughput with the index resident, brute force
+(bf_search) on the same batch, the other metric/k combinations, the
+roofline of the dominant kernel (the grouped stage-2 distance tile) from the
+library's own HIP event timer, and the CPU FP64 oracle timed on a sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_MFMA_PEAK_TF = 157.3   # MI355X dense fp32 matrix peak
+ALU_PEAK_TOPS = 78.6        # fp32 VALU lane-operations per second (157.3 TFLOP/s counts an FMA as 2)
+
+
+def _timed(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--metric", default="l2", choices=["l2", "l1"])
+    ap.add_argument("--k", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=1000,
+                    help="queries of the oracle's timed search sample (0: skip the CPU baseline)")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the other metric / k combinations")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy (byte-counter calibration) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the build has no multi-GPU path (the design for "
+              "sharding by representative is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1103_2635_amd as rbc
+
+    dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": a.numel() * 4}))
+        return
+
+    name = "sub8"
+    w = datagen.WORKLOADS[name]
+    X = datagen.database(name)
+    Q = datagen.queries(name)
+    reps = datagen.representatives(name)
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    m, d = Q.shape
+    n = X.shape[0]
+    sync = torch.cuda.synchronize
+    metric, k = args.metric, args.k
+
+    out = (torch.empty((m, k), dtype=torch.int64, device=dev),
+           torch.empty((m, k), dtype=torch.float32, device=dev))
+    bf_ws = torch.empty(rbc.bf_search_workspace_size(m, n, d, k, metric), dtype=torch.uint8,
+                        device=dev)
+
+    # ---- the step: build + search
+    holder = {}
+
+    def step():
+        ix = rbc.rbc_build(Xd, w.n_r, metric=metric, rep_idx=reps)
+        ws = holder.get("ws")
+        if ws is None:
+            ws = holder["ws"] = torch.empty(rbc.rbc_search_workspace_size(ix, m, k), dtype=torch.uint8,
+                                            device=dev)
+        rbc.rbc_search(ix, Qd, k, out=out, workspace=ws)
+        old = holder.get("ix")
+        if old is not None:
+            old.free()
+        holder["ix"] = ix
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    rbc.timer_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sync()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    tile_ms, tile_n = rbc.timer_read("tile_grouped")
+    kernel_ms = {kn: rbc.timer_read(kn) for kn in ("stage1", "prune", "group", "finalize", "fallback")}
+    rbc.timer_enable(False)
+    ix = holder["ix"]
+
+    # ---- search only (index resident) and its counters
+    ws = holder["ws"]
+    search_ms = _timed(lambda: rbc.rbc_search(ix, Qd, k, out=out, workspace=ws), args.steps,
+                       args.warmup, sync)
+    build_ms = _timed(lambda: rbc.rbc_build(Xd, w.n_r, metric=metric, rep_idx=reps).free(), 3, 1,
+                      sync)
+    stats = rbc.new_stats()
+    rbc.rbc_search(ix, Qd, k, out=out, workspace=ws, stats=stats)
+    sync()
+    st = stats.cpu().numpy()
+    cand = int(st[rbc.STAT_CAND])
+    pairs = int(st[rbc.STAT_PAIRS])
+
+    # ---- brute force on the same batch, with its tile timed by the library
+    rbc.timer_enable(True)
+    bf_ms = _timed(lambda: rbc.bf_search(Qd, Xd, k, metric, out=out, workspace=bf_ws), args.steps,
+                   args.warmup, sync)
+    bf_tile_ms, bf_tile_n = rbc.timer_read("tile")
+    rbc.timer_enable(False)
+
+    def roof(flops_or_elems, ms):
+        if metric == "l2":
+            ach = flops_or_elems / (ms * 1e-3) / 1e12
+            return {"bound": "mfma", "achieved": round(ach, 2), "peak": FP32_MFMA_PEAK_TF,
+                    "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_PEAK_TF, 4)}
+        ach = flops_or_elems / (ms * 1e-3) / 1e12   # lane-ops (2 per element)
+        return {"bound": "alu", "achieved": round(ach, 2), "peak": ALU_PEAK_TOPS,
+                "unit": "Tops/s", "frac": round(ach / ALU_PEAK_TOPS, 4)}
+
+    per_pair = 2 * d  # l2: one multiply-add per feature (2 flops); l1: subtract + abs-add
+    tile_avg = tile_ms / max(tile_n, 1)
+    roofline = roof(per_pair * cand, tile_avg)
+    roofline["traffic"] = None
+    roofline["kernel"] = "tile_l2_mfma grouped (RBC stage 2)" if metric == "l2" else "tile_valu grouped"
+    roofline["avg_ms"] = round(tile_avg, 4)
+    roofline["algorithmic_units"] = "2*d*sum_q candidates = %d flops per launch" % (per_pair * cand)
+    bf_avg = bf_tile_ms / max(bf_tile_n, 1)
+    bf_roof = roof(per_pair * m * n, bf_avg)
+    bf_roof["avg_ms"] = round(bf_avg, 4)
+
+    extra = {}
+    if args.extra:
+        for mt, kk in (("l2", 1), ("l2", 10), ("l1", 1), ("l1", 10)):
+            ix2 = rbc.rbc_build(Xd, w.n_r, metric=mt, rep_idx=reps)
+            o2 = (torch.empty((m, kk), dtype=torch.int64, device=dev),
+                  torch.empty((m, kk), dtype=torch.float32, device=dev))
+            ws2 = torch.empty(rbc.rbc_search_workspace_size(ix2, m, kk), dtype=torch.uint8, device=dev)
+            bws2 = torch.empty(rbc.bf_search_workspace_size(m, n, d, kk, mt), dtype=torch.uint8,
+                               device=dev)
+            s_ms = _timed(lambda: rbc.rbc_search(ix2, Qd, kk, out=o2, workspace=ws2), 5, 2, sync)
+            b_ms = _timed(lambda: rbc.bf_search(Qd, Xd, kk, mt, out=o2, workspace=bws2), 5, 2, sync)
+            extra["%s_k%d" % (mt, kk)] = {"rbc_search_qps": round(m / s_ms * 1e3, 1),
+                                         "bf_qps": round(m / b_ms * 1e3, 1),
+                                         "rbc_search_ms": round(s_ms, 3), "bf_ms": round(b_ms, 3)}
+            ix2.free()
+
+    # ---- CPU FP64 oracle on a bounded sample (build on the full database)
+    cpu = None
+    if args.cpu_sample > 0:
+        import oracle
+
+        samp = min(args.cpu_sample, m)
+        t0 = time.perf_counter()
+        oix = oracle.rbc_build_exact(X, reps, metric)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.rbc_search_exact(Q[:samp], X, oix, k, metric)
+        t_search = time.perf_counter() - t0
+        job_s = t_build + t_search * m / samp
+        cpu = {"value": round(m / job_s, 2), "unit": "queries/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "exact RBC build on all %d points (%.1f s) + search of the first %d of "
+                         "%d queries (%.1f s), scaled to the %d-query job" % (
+                             n, t_build, samp, m, t_search, m)}
+
+    line = {
+        "metric": "exact k-NN queries/s (n=1M, d=64), RBC build+search vs BF, recall 1.0",
+        "value": round(m / ms_step * 1e3, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sub8: n=1,000,000 d=64, 8-dim subspace + N(0,0.01^2) noise, "
+                               "m=10,000 queries, n_r=1,000, %s, k=%d" % (metric, k),
+                   "n": n, "d": d, "m": m, "n_r": w.n_r, "metric": metric, "k": k,
+                   "parallelism": "single GPU"},
+        "search_only_qps": round(m / search_ms * 1e3, 1),
+        "search_ms": round(search_ms, 3),
+        "build_ms": round(build_ms, 3),
+        "bf_qps": round(m / bf_ms * 1e3, 1),
+        "bf_ms": round(bf_ms, 3),
+        "rbc_vs_bf": round(bf_ms / ms_step, 3),
+        "candidates_per_query": round(cand / m, 1),
+        "candidate_fraction": round(cand / (m * n), 4),
+        "pairs_scored_per_query": round(pairs / m, 1),
+        "fallback_queries": int(st[rbc.STAT_FALLBACK]),
+        "kernel_ms_per_step": {kn: round(v[0] / args.steps, 4) for kn, v in kernel_ms.items()},
+        "roofline": roofline,
+        "bf_roofline": bf_roof,
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        line["paths"] = extra
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,17 @@ int rbc_index_export(const rbc_index* index, int64_t* rep_idx, double* psi,
 /* rbc_free -- release an index (NULL is a no-op).  Synchronises the device. */
 void rbc_free(rbc_index* index);
 
+/*
+ * Kernel timing (instrumentation, off by default).  rbc_timer_enable(1)
+ * clears the totals and makes every later call record a pair of HIP events
+ * on its stream around each of its kernels; rbc_timer_read() waits for the
+ * recorded events and returns the summed device time (ms) and launch count
+ * of the kernels called `name`: "tile" (BF distance tile), "tile_grouped"
+ * (RBC stage 2), "finalize", "fallback", "stage1", "prune", "group".
+ */
+int rbc_timer_enable(int on);
+int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);
+
 /* rbc_last_error -- message for the last non-OK return on this thread. */
 const char* rbc_last_error(void);
 

@@ -72,6 +72,9 @@ def lib():
         L.rbc_index_export.argtypes = [_P, _P, _P, _P, _P]
         L.rbc_free.argtypes = [_P]
         L.rbc_free.restype = None
+        L.rbc_timer_enable.argtypes = [ctypes.c_int]
+        L.rbc_timer_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(_I64)]
         _lib = L
     return _lib
 
@@ -247,3 +250,15 @@ def rbc_search(index, Q, k, out=None, workspace=None, **kw):
                             idx.data_ptr(), dist.data_ptr(), workspace.data_ptr(),
                             workspace.numel(), _stream_ptr(Q)))
     return idx, dist
+
+
+def timer_enable(on=True):
+    """Start (or stop) per-kernel HIP event timing inside the library."""
+    _check(lib().rbc_timer_enable(1 if on else 0))
+
+
+def timer_read(name):
+    """(total device ms, launches) of the library kernels called ``name``."""
+    ms, n = ctypes.c_double(), _I64()
+    _check(lib().rbc_timer_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

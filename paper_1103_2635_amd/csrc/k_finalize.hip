@@ -76,23 +76,32 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     const bool valid = lane < C && mi >= 0 && mv < RBC_INF;
     const float a_c = __shfl(mv, C - 1);
 
-    // 2. direct re-score in fp32
+    // 2. direct re-score in fp32: 64 / C lanes per candidate, each summing a
+    //    strided subset of the features, then a reduction inside the group
+    constexpr int LPC = 64 / C;
     const float* qp = a.Q + (int64_t)qrow * a.ldq;
-    const float* xp = a.X + (int64_t)(valid ? mi : 0) * a.ldx;
-    double rho = RBC_INF_D;
-    if (valid) {
-        float s = 0.f;
+    const int cand = lane / LPC;
+    const int sub = lane % LPC;
+    const int32_t crow = __shfl(mi, cand);
+    const bool cvalid = __shfl((int)valid, cand) != 0;
+    float part = 0.f;
+    if (cvalid) {
+        const float* cp = a.X + (int64_t)crow * a.ldx;
         if (a.metric == 0) {
-            for (int f = 0; f < a.d; ++f) {
-                const float t = qp[f] - xp[f];
-                s = __builtin_fmaf(t, t, s);
+            for (int f = sub; f < a.d; f += LPC) {
+                const float t = qp[f] - cp[f];
+                part = __builtin_fmaf(t, t, part);
             }
-            rho = __builtin_sqrt((double)s);
         } else {
-            for (int f = 0; f < a.d; ++f) s += __builtin_fabsf(qp[f] - xp[f]);
-            rho = (double)s;
+            for (int f = sub; f < a.d; f += LPC) part += __builtin_fabsf(qp[f] - cp[f]);
         }
     }
+#pragma unroll
+    for (int off = LPC / 2; off >= 1; off >>= 1) part += __shfl_xor(part, off);
+    const float s32 = __shfl(part, (lane < C ? lane : 0) * LPC);
+    const float* xp = a.X + (int64_t)(valid ? mi : 0) * a.ldx;
+    double rho = RBC_INF_D;
+    if (valid) rho = a.metric == 0 ? __builtin_sqrt((double)s32) : (double)s32;
 
     // 3. float64 re-rank of near-ties
     const double u = 5.9604644775390625e-8;

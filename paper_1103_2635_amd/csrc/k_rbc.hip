@@ -183,12 +183,79 @@ hipError_t launch_psi(const float* X, int64_t ldx, int32_t d, int32_t metric, in
 // --------------------------------------------------------------- stage 1
 // DR[q][r] = rho(q, r) for every query and representative, fp32, direct
 // differences (the BF(q, R) call of Sec. 5.2 keeps every distance).  One
-// thread per query; 32 representatives at a time staged in LDS, features in
-// chunks of 128.
-template <int METRIC>
+// thread per query with the query in registers (d <= 128, KS 16-feature
+// slabs) and 32 representatives at a time staged in LDS; rows of DR have
+// stride ldd (a multiple of 4) and are written as float4.  d > 128 takes the
+// generic kernel below (query features read from memory).
+template <int METRIC, int KS>
 __global__ __launch_bounds__(256) void dist_all_kernel(const float* Q, int64_t ldq, int32_t m,
                                                        const float* R, int64_t ldr, int32_t nr,
-                                                       int32_t d, float* DR) {
+                                                       int32_t d, float* DR, int64_t ldd) {
+    constexpr int F4 = 4 * KS;
+    __shared__ f4 rs[32 * F4];
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const bool qv = q < m;
+    f4 qr[F4];
+    {
+        const float* qp = Q + (int64_t)(qv ? q : 0) * ldq;
+#pragma unroll
+        for (int j = 0; j < F4; ++j) {
+            f4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (4 * j + c < d) v[c] = qp[4 * j + c];
+            qr[j] = v;
+        }
+    }
+    for (int r0 = 0; r0 < nr; r0 += 32) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * F4; e += 256) {
+            const int rr = e / F4, cc = e - rr * F4;
+            f4 v = {0.f, 0.f, 0.f, 0.f};
+            if (r0 + rr < nr && 4 * cc < d) v = *(const f4*)(R + (int64_t)(r0 + rr) * ldr + 4 * cc);
+            rs[e] = v;
+        }
+        __syncthreads();
+        if (!qv) continue;
+        float acc[32];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+            f4 s4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < F4; ++j) {
+                const f4 df = qr[j] - rs[t * F4 + j];
+                if (METRIC == 0) {
+                    s4 = df * df + s4;
+                } else {
+                    s4[0] += __builtin_fabsf(df[0]);
+                    s4[1] += __builtin_fabsf(df[1]);
+                    s4[2] += __builtin_fabsf(df[2]);
+                    s4[3] += __builtin_fabsf(df[3]);
+                }
+            }
+            const float v = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+            acc[t] = METRIC == 0 ? __builtin_sqrtf(v) : v;
+        }
+        float* out = DR + (int64_t)q * ldd + r0;
+        if (r0 + 32 <= nr) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const f4 v = {acc[4 * t], acc[4 * t + 1], acc[4 * t + 2], acc[4 * t + 3]};
+                *(f4*)(out + 4 * t) = v;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 32; ++t)
+                if (r0 + t < nr) out[t] = acc[t];
+        }
+    }
+}
+
+template <int METRIC>
+__global__ __launch_bounds__(256) void dist_all_generic_kernel(const float* Q, int64_t ldq,
+                                                               int32_t m, const float* R,
+                                                               int64_t ldr, int32_t nr, int32_t d,
+                                                               float* DR, int64_t ldd) {
     __shared__ float rs[32][129];
     const int q = blockIdx.x * 256 + threadIdx.x;
     const bool qv = q < m;
@@ -223,18 +290,45 @@ __global__ __launch_bounds__(256) void dist_all_kernel(const float* Q, int64_t l
 #pragma unroll
             for (int j = 0; j < 32; ++j)
                 if (r0 + j < nr)
-                    DR[(int64_t)q * nr + r0 + j] = METRIC == 0 ? __builtin_sqrtf(acc[j]) : acc[j];
+                    DR[(int64_t)q * ldd + r0 + j] = METRIC == 0 ? __builtin_sqrtf(acc[j]) : acc[j];
         }
     }
 }
 
+template <int METRIC>
+static void launch_dist_ks(int ks, dim3 grid, hipStream_t st, const float* Q, int64_t ldq,
+                           int32_t m, const float* R, int64_t ldr, int32_t nr, int32_t d,
+                           float* DR, int64_t ldd) {
+#define RBC_DIST_CASE(K)                                                                        \
+    case K:                                                                                    \
+        hipLaunchKernelGGL((dist_all_kernel<METRIC, K>), grid, dim3(256), 0, st, Q, ldq, m, R, \
+                           ldr, nr, d, DR, ldd);                                               \
+        return;
+    switch (ks) {
+        RBC_DIST_CASE(1)
+        RBC_DIST_CASE(2)
+        RBC_DIST_CASE(3)
+        RBC_DIST_CASE(4)
+        RBC_DIST_CASE(5)
+        RBC_DIST_CASE(6)
+        RBC_DIST_CASE(7)
+        RBC_DIST_CASE(8)
+    }
+#undef RBC_DIST_CASE
+    hipLaunchKernelGGL(dist_all_generic_kernel<METRIC>, grid, dim3(256), 0, st, Q, ldq, m, R, ldr,
+                       nr, d, DR, ldd);
+}
+
 hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, const float* R,
-                           int64_t ldr, int32_t nr, int32_t d, float* DR, hipStream_t st) {
+                           int64_t ldr, int32_t nr, int32_t d, float* DR, int64_t ldd,
+                           hipStream_t st) {
     const dim3 grid((m + 255) / 256);
+    // the register path needs 16-byte aligned representative rows
+    const int ks = (ldr % 4 == 0 && ((uintptr_t)R & 15) == 0) ? (d + 15) / 16 : 0;
     if (metric == 0)
-        hipLaunchKernelGGL(dist_all_kernel<0>, grid, dim3(256), 0, st, Q, ldq, m, R, ldr, nr, d, DR);
+        launch_dist_ks<0>(ks, grid, st, Q, ldq, m, R, ldr, nr, d, DR, ldd);
     else
-        hipLaunchKernelGGL(dist_all_kernel<1>, grid, dim3(256), 0, st, Q, ldq, m, R, ldr, nr, d, DR);
+        launch_dist_ks<1>(ks, grid, st, Q, ldq, m, R, ldr, nr, d, DR, ldd);
     return hipGetLastError();
 }
 
@@ -248,14 +342,15 @@ hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, c
 //   prune r when  lo(q, r) - psi_r > gamma_k_up          (rule 1, strict)
 //             or  lo(q, r) > 2 gamma_k_up + gamma_1_up    (rule 2, k-NN form)
 // A superset of the exactly-kept lists is kept, so the answer is unchanged.
-__global__ __launch_bounds__(256) void prune_kernel(const float* DR, int32_t m, int32_t nr,
-                                                    int32_t k, double delta, const double* psi,
+__global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd, int32_t m,
+                                                    int32_t nr, int32_t k, double delta,
+                                                    const double* psi,
                                                     const int32_t* list_off, uint8_t* keep,
                                                     int32_t* nearest, int64_t* stats) {
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= m) return;
-    const float* row = DR + (int64_t)q * nr;
+    const float* row = DR + (int64_t)q * ldd;
 
     // gamma_1 and its position
     float bv = RBC_INF;
@@ -321,11 +416,11 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int32_t m, 
     }
 }
 
-hipError_t launch_prune(const float* DR, int32_t m, int32_t nr, int32_t k, double delta,
-                        const double* psi, const int32_t* list_off, uint8_t* keep,
+hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k,
+                        double delta, const double* psi, const int32_t* list_off, uint8_t* keep,
                         int32_t* nearest, int64_t* stats, hipStream_t st) {
-    hipLaunchKernelGGL(prune_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, m, nr, k, delta, psi,
-                       list_off, keep, nearest, stats);
+    hipLaunchKernelGGL(prune_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, ldd, m, nr, k, delta,
+                       psi, list_off, keep, nearest, stats);
     return hipGetLastError();
 }
 

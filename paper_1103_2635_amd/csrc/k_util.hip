@@ -57,29 +57,36 @@ hipError_t launch_repack(const float* A, int64_t rows, int64_t lda, int32_t d, f
     return hipGetLastError();
 }
 
-// Squared norm of every row (16 lanes per row, fp32), and the largest row norm
-// as float bits through an integer atomic max (valid for non-negative floats).
-// rowmap (optional) gives the source row of output row i.
+// Squared norm of every row (16 lanes per row, fp32), and the largest row
+// norm as float bits through an integer atomic max (valid for non-negative
+// floats).  A bounded grid strides over the rows so that each workgroup
+// issues one atomic.  rowmap (optional) gives the source row of output row i.
+constexpr int kNormBlocks = 1024;
+
 __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t rows, int64_t lda,
                                                         int32_t d, const int32_t* rowmap,
                                                         float* out, uint32_t* maxbits) {
+    __shared__ float wmax[4];
     const int sub = threadIdx.x & 15;
-    const int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
-    float s = 0.f;
-    if (r < rows) {
+    float nmax = 0.f;
+    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4; r < rows;
+         r += ((int64_t)gridDim.x * blockDim.x) >> 4) {
         const int64_t src = rowmap ? rowmap[r] : r;
         const float* p = A + src * lda;
+        float s = 0.f;
         for (int f = sub; f < d; f += 16) s = __builtin_fmaf(p[f], p[f], s);
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
+        if (sub == 0) out[r] = s;
+        nmax = fmaxf(nmax, __builtin_sqrtf(s));
     }
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
-    if (r < rows && sub == 0) out[r] = s;
     if (maxbits) {
-        float nv = r < rows ? __builtin_sqrtf(s) : 0.f;
 #pragma unroll
-        for (int off = 32; off >= 16; off >>= 1) nv = fmaxf(nv, __shfl_xor(nv, off));
-        // lanes 0..15 of each wavefront now hold the wavefront max
-        if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(nv));
+        for (int off = 32; off >= 1; off >>= 1) nmax = fmaxf(nmax, __shfl_xor(nmax, off));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = nmax;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax(maxbits, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
     }
 }
 
@@ -87,7 +94,8 @@ hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d
                             const int32_t* rowmap, float* out, uint32_t* maxbits,
                             hipStream_t st) {
     if (rows <= 0) return hipSuccess;
-    const int64_t blocks = (rows * 16 + 255) / 256;
+    int64_t blocks = (rows * 16 + 255) / 256;
+    if (blocks > kNormBlocks) blocks = kNormBlocks;
     hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, rows, lda,
                        d, rowmap, out, maxbits);
     return hipGetLastError();

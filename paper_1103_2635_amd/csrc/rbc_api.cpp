@@ -165,11 +165,15 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_
         a.pidx = w.pidx;
         a.stats = stats;
         const dim3 grid(p.nqblk, p.nsplit);
-        if (p.path == kPathMfma)
-            rc = hip_status(launch_tile_mfma(p.ks, p.c, grp != nullptr, grid, a, st), "tile (mfma)");
-        else
-            rc = hip_status(launch_tile_valu(p.metric, p.ks, p.c, grp != nullptr, grid, a, st),
-                            "tile (valu)");
+        {
+            KernelTimer kt(grp ? "tile_grouped" : "tile", st);
+            if (p.path == kPathMfma)
+                rc = hip_status(launch_tile_mfma(p.ks, p.c, grp != nullptr, grid, a, st),
+                                "tile (mfma)");
+            else
+                rc = hip_status(launch_tile_valu(p.metric, p.ks, p.c, grp != nullptr, grid, a, st),
+                                "tile (valu)");
+        }
         if (rc) return rc;
 
         FinArgs f;
@@ -195,7 +199,10 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_
         f.fb_list = w.fb_list;
         f.fb_count = fb_count;
         f.stats = stats;
-        rc = hip_status(launch_finalize(p.c, f, st), "finalize");
+        {
+            KernelTimer kt("finalize", st);
+            rc = hip_status(launch_finalize(p.c, f, st), "finalize");
+        }
         if (rc) return rc;
     }
     ExactArgs e;
@@ -214,6 +221,7 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_
     e.out_idx = out_idx;
     e.out_dist = out_dist;
     int grid = p.path == kPathExact ? (int)std::min<int64_t>(m, 2048) : kFallbackBlocks;
+    KernelTimer kt("fallback", st);
     return hip_status(launch_exact(e, grid, st), "exact fallback");
 }
 

@@ -74,6 +74,20 @@ struct GroupedArgs {
     int32_t n_r;
 };
 
+// Records a pair of HIP events around a launch when timing is enabled
+// (rbc_timer_enable); the scope is the launch.
+class KernelTimer {
+public:
+    KernelTimer(const char* name, hipStream_t st);
+    ~KernelTimer();
+
+private:
+    const char* name_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+    bool active_ = false;
+};
+
 int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int32_t metric,
                  int32_t k, const rbc_search_opts* opts, BfPlan* p);
 void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w);

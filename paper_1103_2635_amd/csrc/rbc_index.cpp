@@ -182,7 +182,7 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
     carve_bf(p, m, ix->rows, cv, &w->bf);
     if (p.path == kPathExact) return;
     const int64_t nr = ix->n_r;
-    w->DR = cv.take<float>(m * nr);
+    w->DR = cv.take<float>(m * ((nr + 3) / 4 * 4));
     w->keep = cv.take<uint8_t>(m * nr);
     w->nearest = cv.take<int32_t>(m);
     w->qmap = cv.take<int32_t>(m);
@@ -311,17 +311,27 @@ int rbc_search(const rbc_index* ix, const float* Q, int64_t m, int64_t ldq, int3
         const int32_t nr = (int32_t)ix->n_r;
         const double u = 5.9604644775390625e-8;
         const double delta = 2.0 * (ix->d + 2) * u;
-        if ((rc = check(launch_dist_all(ix->metric, Q, ldq, (int32_t)m, ix->R, ix->ld, nr, ix->d,
-                                        w.DR, st), "stage 1")))
-            return rc;
-        if ((rc = check(launch_prune(w.DR, (int32_t)m, nr, k, delta, ix->psi, ix->list_off, w.keep,
-                                     w.nearest, stats, st), "prune")))
-            return rc;
-        if ((rc = check(launch_csort(w.nearest, m, nr, w.cnt, w.qmap, nullptr, st), "group")))
-            return rc;
-        if ((rc = check(launch_block_union(w.keep, w.qmap, (int32_t)m, nr, ix->list_off,
-                                           w.blk_reps, w.blk_cnt, w.blk_pre, st), "union")))
-            return rc;
+        const int64_t ldd = ((int64_t)nr + 3) / 4 * 4;  // row stride of the stage-1 distances
+        {
+            KernelTimer kt("stage1", st);
+            if ((rc = check(launch_dist_all(ix->metric, Q, ldq, (int32_t)m, ix->R, ix->ld, nr,
+                                            ix->d, w.DR, ldd, st), "stage 1")))
+                return rc;
+        }
+        {
+            KernelTimer kt("prune", st);
+            if ((rc = check(launch_prune(w.DR, ldd, (int32_t)m, nr, k, delta, ix->psi,
+                                         ix->list_off, w.keep, w.nearest, stats, st), "prune")))
+                return rc;
+        }
+        {
+            KernelTimer kt("group", st);
+            if ((rc = check(launch_csort(w.nearest, m, nr, w.cnt, w.qmap, nullptr, st), "group")))
+                return rc;
+            if ((rc = check(launch_block_union(w.keep, w.qmap, (int32_t)m, nr, ix->list_off,
+                                               w.blk_reps, w.blk_cnt, w.blk_pre, st), "union")))
+                return rc;
+        }
         GroupedArgs g;
         g.blk_reps = w.blk_reps;
         g.blk_cnt = w.blk_cnt;

@@ -21,9 +21,10 @@ hipError_t launch_psi(const float* X, int64_t ldx, int32_t d, int32_t metric, in
                       const int32_t* owner, const float* R, int64_t ldr, double* psi,
                       hipStream_t st);
 hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, const float* R,
-                           int64_t ldr, int32_t nr, int32_t d, float* DR, hipStream_t st);
-hipError_t launch_prune(const float* DR, int32_t m, int32_t nr, int32_t k, double delta,
-                        const double* psi, const int32_t* list_off, uint8_t* keep,
+                           int64_t ldr, int32_t nr, int32_t d, float* DR, int64_t ldd,
+                           hipStream_t st);
+hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k,
+                        double delta, const double* psi, const int32_t* list_off, uint8_t* keep,
                         int32_t* nearest, int64_t* stats, hipStream_t st);
 hipError_t launch_block_union(const uint8_t* keep, const int32_t* qmap, int32_t m, int32_t nr,
                               const int32_t* list_off, int32_t* blk_reps, int32_t* blk_cnt,
