@@ -119,8 +119,8 @@ def main():
         step()
     sync()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    tile_ms, tile_n = rbc.timer_read("tile_grouped")
-    kernel_ms = {kn: rbc.timer_read(kn) for kn in ("stage1", "prune", "group", "finalize", "fallback")}
+    tile_ms, tile_n = rbc.timer_read("tile_items")
+    kernel_ms = {kn: rbc.timer_read(kn) for kn in ("stage1", "prune", "worklist", "finalize", "fallback")}
     rbc.timer_enable(False)
     ix = holder["ix"]
 
@@ -157,7 +157,7 @@ def main():
     tile_avg = tile_ms / max(tile_n, 1)
     roofline = roof(per_pair * cand, tile_avg)
     roofline["traffic"] = None
-    roofline["kernel"] = "tile_l2_mfma grouped (RBC stage 2)" if metric == "l2" else "tile_valu grouped"
+    roofline["kernel"] = "tile_l2_mfma_items (RBC stage 2)" if metric == "l2" else "tile_valu_items (RBC stage 2)"
     roofline["avg_ms"] = round(tile_avg, 4)
     roofline["algorithmic_units"] = "2*d*sum_q candidates = %d flops per launch" % (per_pair * cand)
     bf_avg = bf_tile_ms / max(bf_tile_n, 1)

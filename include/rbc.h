@@ -187,8 +187,8 @@ void rbc_free(rbc_index* index);
  * clears the totals and makes every later call record a pair of HIP events
  * on its stream around each of its kernels; rbc_timer_read() waits for the
  * recorded events and returns the summed device time (ms) and launch count
- * of the kernels called `name`: "tile" (BF distance tile), "tile_grouped"
- * (RBC stage 2), "finalize", "fallback", "stage1", "prune", "group".
+ * of the kernels called `name`: "tile" (BF distance tile), "tile_items"
+ * (RBC stage 2), "finalize", "fallback", "stage1", "prune", "worklist".
  */
 int rbc_timer_enable(int on);
 int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);

@@ -19,57 +19,73 @@
 
 namespace rbc {
 
+// Wavefront argmin of (value, id, lane); every lane gets the winner's lane.
+__device__ __forceinline__ int wave_argmin(float v, int32_t id, float& bv, int32_t& bi) {
+    bv = v;
+    bi = id;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ov = __shfl_xor(bv, off);
+        const int32_t oi = __shfl_xor(bi, off);
+        if (ov < bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    const uint64_t m = __ballot(v == bv && id == bi);
+    return (int)__builtin_ctzll(m);
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     const int lane = threadIdx.x & 63;
     const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (slot >= a.m) return;  // uniform per wavefront
-    const int qrow = a.qmap ? a.qmap[slot] : slot;
-    const int64_t stride = (int64_t)a.m * C;
+    const int qrow = slot;
 
-    // 1. merge the sorted partial lists (lane s < nsplit reads list s)
+    // 1. merge the sorted partial lists into the c best entries: lane r ends
+    //    up holding merged entry r.  Each round takes the smallest head; one
+    //    lane (the lowest among equal heads) advances, so copies of a bound
+    //    are counted as often as they occur.
     float mv = RBC_INF;
     int32_t mi = -1;
-    if (a.nsplit == 1) {
+    if (a.qoff == nullptr && a.nsplit == 1) {
         if (lane < C) {
             mv = a.pval[(int64_t)slot * C + lane];
             mi = a.pidx[(int64_t)slot * C + lane];
         }
     } else {
-        int ptr = 0;
-        float hv = RBC_INF;
-        int32_t hi = 0x7fffffff;
-        const float* lv = a.pval + (int64_t)lane * stride + (int64_t)slot * C;
-        const int32_t* li = a.pidx + (int64_t)lane * stride + (int64_t)slot * C;
-        if (lane < a.nsplit) {
-            hv = lv[0];
-            hi = li[0];
+        // every lane first reduces its share of the lists to one sorted
+        // register list of c entries (a list is sorted, so its scan stops at
+        // the first entry that cannot enter)
+        TopC<C> loc;
+        loc.init();
+        const int nl = a.qoff ? a.npairs[slot] : a.nsplit;
+        for (int j = lane; j < nl; j += 64) {
+            const int64_t base = a.qoff ? ((int64_t)a.qoff[slot] + j) * C
+                                        : ((int64_t)j * a.m + slot) * C;
+            for (int i = 0; i < C; ++i) {
+                const float v = a.pval[base + i];
+                if (!(v < loc.worst())) break;
+                loc.insert(v, a.pidx[base + i]);
+            }
         }
         for (int r = 0; r < C; ++r) {
-            float bv = hv;
-            int32_t bi = hi;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const float ov = __shfl_xor(bv, off);
-                const int32_t oi = __shfl_xor(bi, off);
-                if (ov < bv || (ov == bv && oi < bi)) {
-                    bv = ov;
-                    bi = oi;
-                }
-            }
+            float bv;
+            int32_t bi;
+            const int w = wave_argmin(loc.v[0], loc.i[0], bv, bi);
             if (lane == r) {
                 mv = bv;
                 mi = bi;
             }
-            if (lane < a.nsplit && hv == bv && hi == bi) {
-                ++ptr;
-                if (ptr < C) {
-                    hv = lv[ptr];
-                    hi = li[ptr];
-                } else {
-                    hv = RBC_INF;
-                    hi = 0x7fffffff;
+            if (lane == w) {
+#pragma unroll
+                for (int j = 0; j + 1 < C; ++j) {
+                    loc.v[j] = loc.v[j + 1];
+                    loc.i[j] = loc.i[j + 1];
                 }
+                loc.v[C - 1] = RBC_INF;
+                loc.i[C - 1] = -1;
             }
         }
     }

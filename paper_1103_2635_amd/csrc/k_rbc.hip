@@ -333,164 +333,215 @@ hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, c
 }
 
 // ------------------------------------------------------- pruning (Sec. 5.2)
-// One wavefront per query.  gamma_1 = the smallest representative distance
-// (its position is the query's nearest representative), gamma_k = the k-th
-// smallest (+inf when k > n_r), found by a bitwise search over the float bit
-// patterns (non-negative floats order like their bits).  The stored fp32
+// One wavefront per query.  gamma_1 = the smallest representative distance,
+// gamma_k = the k-th smallest (+inf when k > n_r) and gamma_c = the c-th
+// smallest (the shortlist length), found by a bitwise search over the float
+// bit patterns (non-negative floats order like their bits).  The stored fp32
 // distances are within a relative delta of the true ones, so the rules are
 // applied to lower bounds of rho(q, r) and upper bounds of gamma:
 //   prune r when  lo(q, r) - psi_r > gamma_k_up          (rule 1, strict)
 //             or  lo(q, r) > 2 gamma_k_up + gamma_1_up    (rule 2, k-NN form)
 // A superset of the exactly-kept lists is kept, so the answer is unchanged.
+// Since R is a subset of X, gamma_c_up also bounds the distance of q's c-th
+// nearest database point; it seeds the stage-2 shortlists.
+// Outputs: lrank[q][r] = rank of r among the lists q keeps (-1: pruned),
+// keep_rq[r][q] (representative-major copy of the keep bits), nkept[q],
+// gcup[q].
 __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd, int32_t m,
-                                                    int32_t nr, int32_t k, double delta,
-                                                    const double* psi,
-                                                    const int32_t* list_off, uint8_t* keep,
-                                                    int32_t* nearest, int64_t* stats) {
+                                                    int32_t nr, int32_t k, int32_t c,
+                                                    double delta, const double* psi,
+                                                    const int32_t* list_off, int32_t* lrank,
+                                                    uint8_t* keep_rq, int32_t* nkept, float* gcup,
+                                                    int64_t* stats) {
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= m) return;
     const float* row = DR + (int64_t)q * ldd;
 
-    // gamma_1 and its position
-    float bv = RBC_INF;
-    int32_t bi = 0x7fffffff;
-    for (int r = lane; r < nr; r += 64) {
-        const float v = row[r];
-        if (v < bv) {
-            bv = v;
-            bi = r;
-        }
-    }
+    float g1 = RBC_INF;
+    for (int r = lane; r < nr; r += 64) g1 = fminf(g1, row[r]);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const float ov = __shfl_xor(bv, off);
-        const int32_t oi = __shfl_xor(bi, off);
-        if (ov < bv || (ov == bv && oi < bi)) {
-            bv = ov;
-            bi = oi;
+    for (int off = 32; off >= 1; off >>= 1) g1 = fminf(g1, __shfl_xor(g1, off));
+    // gamma_k and gamma_c: smallest bit pattern p with count(v <= p) >= k (c)
+    uint32_t pk = 0, pc = 0;
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t tk = pk | (1u << bit), tc = pc | (1u << bit);
+        int ck = 0, cc = 0;
+        for (int r = lane; r < nr; r += 64) {
+            const uint32_t b = __float_as_uint(row[r]);
+            ck += b < tk ? 1 : 0;
+            cc += b < tc ? 1 : 0;
         }
-    }
-    const float g1 = bv;
-    // gamma_k: smallest bit pattern p with count(v <= p) >= k
-    float gk = RBC_INF;
-    if (k <= nr) {
-        uint32_t prefix = 0;
-        for (int bit = 31; bit >= 0; --bit) {
-            const uint32_t trial = prefix | (1u << bit);
-            // count of values strictly below trial
-            int c = 0;
-            for (int r = lane; r < nr; r += 64) c += __float_as_uint(row[r]) < trial ? 1 : 0;
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
-            if (c < k) prefix = trial;
+        for (int off = 32; off >= 1; off >>= 1) {
+            ck += __shfl_xor(ck, off);
+            cc += __shfl_xor(cc, off);
         }
-        gk = __uint_as_float(prefix);
+        if (ck < k) pk = tk;
+        if (cc < c) pc = tc;
     }
+    const float gk = k <= nr ? __uint_as_float(pk) : RBC_INF;
+    const float gc = c <= nr ? __uint_as_float(pc) : RBC_INF;
     const double g1_up = (double)g1 * (1.0 + delta);
     const double gk_up = (double)gk * (1.0 + delta);
     const double bound2 = 2.0 * gk_up + g1_up;
-    int nkept = 0;
+    int running = 0;
     int64_t ncand = 0;
-    for (int r = lane; r < nr; r += 64) {
-        const double lo = (double)row[r] * (1.0 - delta);
-        const double ps = psi[r] * (1.0 + 1e-15);
-        const bool prune = (lo - ps > gk_up) || (lo > bound2);
-        keep[(int64_t)q * nr + r] = prune ? 0 : 1;
-        if (!prune) {
-            ++nkept;
-            ncand += list_off[r + 1] - list_off[r];
+    for (int base = 0; base < nr; base += 64) {
+        const int r = base + lane;
+        bool kept = false;
+        if (r < nr) {
+            const double lo = (double)row[r] * (1.0 - delta);
+            const double ps = psi[r] * (1.0 + 1e-15);
+            kept = !((lo - ps > gk_up) || (lo > bound2));
         }
+        const uint64_t bits = __ballot(kept);
+        const uint64_t below = lane ? (bits & (~0ull >> (64 - lane))) : 0ull;
+        if (r < nr) {
+            lrank[(int64_t)q * nr + r] = kept ? running + __popcll(below) : -1;
+            keep_rq[(int64_t)r * m + q] = kept ? 1 : 0;
+            if (kept) ncand += list_off[r + 1] - list_off[r];
+        }
+        running += __popcll(bits);
     }
-    if (lane == 0) nearest[q] = bi;
+    if (lane == 0) {
+        nkept[q] = running;
+        gcup[q] = gc < RBC_INF ? (float)((double)gc * (1.0 + delta)) * (1.0f + 1e-6f) : RBC_INF;
+    }
     if (stats) {
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            nkept += __shfl_xor(nkept, off);
-            ncand += __shfl_xor(ncand, off);
-        }
+        for (int off = 32; off >= 1; off >>= 1) ncand += __shfl_xor(ncand, off);
         if (lane == 0) {
-            atomicAdd((unsigned long long*)&stats[3], (unsigned long long)nkept);
+            atomicAdd((unsigned long long*)&stats[3], (unsigned long long)running);
             atomicAdd((unsigned long long*)&stats[4], (unsigned long long)ncand);
         }
     }
 }
 
-hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k,
-                        double delta, const double* psi, const int32_t* list_off, uint8_t* keep,
-                        int32_t* nearest, int64_t* stats, hipStream_t st) {
-    hipLaunchKernelGGL(prune_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, ldd, m, nr, k, delta,
-                       psi, list_off, keep, nearest, stats);
+hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
+                        double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
+                        uint8_t* keep_rq, int32_t* nkept, float* gcup, int64_t* stats,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(prune_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, ldd, m, nr, k, c,
+                       delta, psi, list_off, lrank, keep_rq, nkept, gcup, stats);
     return hipGetLastError();
 }
 
-// ------------------------------------------------- per-block union of lists
-// For query block b (slots b*256 ..), the representatives kept by at least one
-// of its queries, in ascending order, and the running row count before each.
-__global__ __launch_bounds__(256) void block_union_kernel(const uint8_t* keep, const int32_t* qmap,
-                                                          int32_t m, int32_t nr,
-                                                          const int32_t* list_off,
-                                                          int32_t* blk_reps, int32_t* blk_cnt,
-                                                          int64_t* blk_pre) {
-    extern __shared__ uint8_t flags[];
-    __shared__ int32_t cpart[256];
-    __shared__ int64_t rpart[256];
-    const int b = blockIdx.x;
-    const int t = threadIdx.x;
-    for (int r = t; r < nr; r += 256) flags[r] = 0;
-    __syncthreads();
-    const int slot = b * 256 + t;
-    if (slot < m) {
-        const uint8_t* kr = keep + (int64_t)qmap[slot] * nr;
-        for (int r = 0; r < nr; ++r)
-            if (kr[r]) flags[r] = 1;
-    }
-    __syncthreads();
-    // thread t owns the representative range [t * chunk, (t + 1) * chunk)
-    const int chunk = (nr + 255) / 256;
-    const int r0 = t * chunk;
-    const int r1 = r0 + chunk < nr ? r0 + chunk : nr;
+// ------------------------------------------------ stage-2 work list (items)
+// Per representative (one wavefront each): how many queries kept it, and the
+// number of 256-query items it makes.
+__global__ __launch_bounds__(256) void rep_count_kernel(const uint8_t* keep_rq, int32_t m,
+                                                        int32_t nr, int32_t* cnt, int32_t* nitems) {
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nr) return;
+    const uint8_t* kr = keep_rq + (int64_t)r * m;
     int c = 0;
-    int64_t rows = 0;
-    for (int r = r0; r < r1; ++r)
-        if (flags[r]) {
-            ++c;
-            rows += list_off[r + 1] - list_off[r];
-        }
-    cpart[t] = c;
-    rpart[t] = rows;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int32_t ca = t >= off ? cpart[t - off] : 0;
-        const int64_t ra = t >= off ? rpart[t - off] : 0;
-        __syncthreads();
-        cpart[t] += ca;
-        rpart[t] += ra;
-        __syncthreads();
-    }
-    int pos = t > 0 ? cpart[t - 1] : 0;
-    int64_t pre = t > 0 ? rpart[t - 1] : 0;
-    int32_t* reps = blk_reps + (int64_t)b * nr;
-    int64_t* prefix = blk_pre + (int64_t)b * (nr + 1);
-    for (int r = r0; r < r1; ++r)
-        if (flags[r]) {
-            reps[pos] = r;
-            prefix[pos] = pre;
-            ++pos;
-            pre += list_off[r + 1] - list_off[r];
-        }
-    if (t == 255) {
-        blk_cnt[b] = cpart[255];
-        prefix[cpart[255]] = rpart[255];
+    for (int q = lane; q < m; q += 64) c += kr[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if (lane == 0) {
+        cnt[r] = c;
+        nitems[r] = (c + kTileQ - 1) / kTileQ;
     }
 }
 
-hipError_t launch_block_union(const uint8_t* keep, const int32_t* qmap, int32_t m, int32_t nr,
-                              const int32_t* list_off, int32_t* blk_reps, int32_t* blk_cnt,
-                              int64_t* blk_pre, hipStream_t st) {
-    const int nblk = (m + 255) / 256;
-    hipLaunchKernelGGL(block_union_kernel, dim3(nblk), dim3(256), (size_t)nr, st, keep, qmap, m, nr,
-                       list_off, blk_reps, blk_cnt, blk_pre);
+// The queries that kept r, ascending, at qlist[roff[r] ..].
+__global__ __launch_bounds__(256) void rep_fill_kernel(const uint8_t* keep_rq, int32_t m,
+                                                       int32_t nr, const int32_t* roff,
+                                                       int32_t* qlist) {
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nr) return;
+    const uint8_t* kr = keep_rq + (int64_t)r * m;
+    int pos = roff[r];
+    for (int base = 0; base < m; base += 64) {
+        const int q = base + lane;
+        const bool kept = q < m && kr[q] != 0;
+        const uint64_t bits = __ballot(kept);
+        const uint64_t below = lane ? (bits & (~0ull >> (64 - lane))) : 0ull;
+        if (kept) qlist[pos + __popcll(below)] = q;
+        pos += __popcll(bits);
+    }
+}
+
+// In-place exclusive scan of v[0 .. n) by one workgroup; v[n] = the total.
+__global__ __launch_bounds__(1024) void scan_total_kernel(int32_t* v, int64_t n) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t s = t * chunk;
+    const int64_t e = s + chunk < n ? s + chunk : n;
+    int64_t acc = 0;
+    for (int64_t i = s; i < e; ++i) acc += v[i];
+    part[t] = acc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t add = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? part[t - 1] : 0;
+    for (int64_t i = s; i < e; ++i) {
+        const int32_t x = v[i];
+        v[i] = (int32_t)run;
+        run += x;
+    }
+    if (t == 1023) v[n] = (int32_t)part[1023];
+}
+
+hipError_t launch_scan_total(int32_t* v, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1024), 0, st, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_t* roff,
+                           int32_t* ioff, int32_t* qlist, hipStream_t st) {
+    const dim3 grid((nr + 3) / 4);
+    hipLaunchKernelGGL(rep_count_kernel, grid, dim3(256), 0, st, keep_rq, m, nr, roff, ioff);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_scan_total(roff, nr, st)) != hipSuccess) return e;
+    if ((e = launch_scan_total(ioff, nr, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rep_fill_kernel, grid, dim3(256), 0, st, keep_rq, m, nr,
+                       (const int32_t*)roff, qlist);
+    return hipGetLastError();
+}
+
+// Stage-2 shortlist threshold per query, in the value space of the tile:
+//   mode 0 (matrix-core l2, values ||x||^2 - 2 q.x):
+//        gc^2 - ||q||^2 + 2 E,  E = 4 (d + 2) u (||q|| + max ||x||)^2
+//   mode 1 (direct l2, values d^2):  gc^2 (1 + delta)
+//   mode 2 (direct l1, values rho):  gc (1 + delta)
+// each widened by a relative 4e-6; +inf when gc is.
+__global__ void tau_kernel(const float* gcup, const float* qn, const uint32_t* xmax_bits,
+                           int32_t m, int32_t d, int32_t mode, double delta, float* tau) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const double gc = (double)gcup[q];
+    float t = RBC_INF;
+    if (gc < RBC_INF_D) {
+        double v;
+        if (mode == 0) {
+            const double n2 = (double)qn[q];
+            const double sq = __builtin_sqrt(n2) + (double)__uint_as_float(*xmax_bits);
+            const double e = 4.0 * (d + 2) * 5.9604644775390625e-8 * sq * sq;
+            v = gc * gc * (1.0 + 4e-6) - n2 + 2.0 * e;
+        } else if (mode == 1) {
+            v = gc * gc * (1.0 + delta) * (1.0 + 4e-6);
+        } else {
+            v = gc * (1.0 + delta) * (1.0 + 4e-6);
+        }
+        t = (float)v;
+    }
+    tau[q] = t;
+}
+
+hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits, int32_t m,
+                      int32_t d, int32_t mode, double delta, float* tau, hipStream_t st) {
+    hipLaunchKernelGGL(tau_kernel, dim3((m + 255) / 256), dim3(256), 0, st, gcup, qn, xmax_bits, m,
+                       d, mode, delta, tau);
     return hipGetLastError();
 }
 

@@ -1,9 +1,9 @@
 // k_tile_mfma.hip -- L2 distance tile on the gfx950 matrix cores.
 //
 // Sec. 3 observes that the distance step of BF(Q, X) is shaped like a
-// matrix product.  For the Euclidean metric the ranking of
-// database rows for a fixed query q only needs  val(x) = ||x||^2 - 2 q.x
-// (||q||^2 is common to all rows), a dense contraction over the d features.
+// matrix product.  For the Euclidean metric the ranking of database rows for
+// a fixed query q only needs  val(x) = ||x||^2 - 2 q.x  (||q||^2 is common to
+// all rows), a dense contraction over the d features.
 //
 // Layout of one wavefront's tile (v_mfma_f32_16x16x4f32, fp32 in / fp32
 // accumulate): rows of the MFMA output are 32 database rows (two 16-row
@@ -12,12 +12,21 @@
 // (exact), so the MFMA result is val directly.  Which feature feeds which
 // k-slot of an MFMA is free as long as both operands agree: lane l loads the
 // float4 at features 16s + 4(l/16) of its row (one 64-byte segment per row per
-// slab) and uses its four components in four consecutive MFMAs.
+// slab) and uses its four components in four consecutive MFMAs.  The database
+// fragments of the next 32 rows are loaded while the current ones are used.
 //
 // The comparison step (per-query top-c) needs one query per lane, so each
 // 32x64 block of results goes through a wavefront-private LDS tile (written as
 // [query][row], read back one query per lane), then every lane pushes its 32
 // values into a sorted register shortlist (TopC).
+//
+// Two launch forms share the row scan:
+//   BF mode    -- grid (query blocks, database splits); a workgroup's 256
+//                 queries scan one split of the rows.
+//   item mode  -- exact RBC stage 2, a persistent grid pulling work items
+//                 (representative r, 256 of the queries that kept r) from a
+//                 queue; the queries scan the rows of L_r, their shortlists
+//                 start at a per-query threshold known from stage 1.
 #include "rbc_device.h"
 
 #ifndef RBC_KS
@@ -31,142 +40,210 @@ constexpr int kTStride = 36;  // floats per query row of the transpose tile
 // Two workgroups per CU while the register footprint allows it.
 template <int KS, int C>
 struct MfmaOcc {
-    static constexpr int value = (24 * KS + 2 * C + 64 <= 200) ? 2 : 1;
+    static constexpr int value = (32 * KS + 2 * C + 64 <= 232) ? 2 : 1;
 };
 
-template <int KS, int C, bool GROUPED>
-__global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma(TileArgs a) {
-    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4;
-    const int c16 = lane & 15;
-    const int qblk = blockIdx.x;
-    const int split = blockIdx.y;
-    const int slot0 = qblk * kTileQ + wave * kWave;
-    float* tb = tbuf[wave];
-
-    // Query fragments: qf[qb][s] = -2 * Q[slot0 + 16 qb + c16][16 s + 4 g .. + 3].
-    f4 qf[4][KS];
+// Query fragments: qf[qb][s] = -2 * Q[qrow[qb]][16 s + 4 g .. + 3].
+template <int KS>
+__device__ __forceinline__ void load_qfrag(f4 (&qf)[4][KS], const float* Q, int64_t ldq, int d,
+                                           const int (&qrow)[4], int g) {
 #pragma unroll
     for (int qb = 0; qb < 4; ++qb) {
-        const int slot = slot0 + 16 * qb + c16;
-        const int qs = slot < a.m ? slot : a.m - 1;
-        const int qrow = a.qmap ? a.qmap[qs] : qs;
-        const float* qp = a.Q + (int64_t)qrow * a.ldq;
+        const float* qp = Q + (int64_t)qrow[qb] * ldq;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int f = 16 * s + 4 * g;
             f4 v = {0.f, 0.f, 0.f, 0.f};
-            if (f < a.d) v = *(const f4*)(qp + f);
+            if (f < d) v = *(const f4*)(qp + f);
             qf[qb][s] = v * -2.0f;
         }
     }
+}
 
-    const int myslot = slot0 + lane;
-    const bool qvalid = myslot < a.m;
-    int myrow = 0;
-    if (GROUPED && qvalid) myrow = a.qmap ? a.qmap[myslot] : myslot;
+template <int KS>
+__device__ __forceinline__ void load_xfrag(f4 (&xa)[2][KS], const float* X, int64_t ldx, int n,
+                                           int d, int base, int c16, int g) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        int row = base + 16 * rb + c16;
+        row = row < n ? row : n - 1;
+        const float* xp = X + (int64_t)row * ldx;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int f = 16 * s + 4 * g;
+            f4 v = {0.f, 0.f, 0.f, 0.f};
+            if (f < d) v = *(const f4*)(xp + f);
+            xa[rb][s] = v;
+        }
+    }
+}
 
-    TopC<C> top;
-    top.init();
-    int64_t pairs = 0;
-
-    for_each_segment(a, qblk, split, [&](int32_t r0, int32_t r1, int32_t rep) {
-        bool act = qvalid;
-        if (GROUPED) act = act && a.keep[(int64_t)myrow * a.n_r + rep] != 0;
-        const uint64_t any = __ballot(act);
-        if (any == 0) return;  // no query of this wavefront kept the list
-        if (GROUPED && lane == 0) pairs += (int64_t)__popcll(any) * (r1 - r0);
-
-        for (int32_t base = r0; base < r1; base += kRowsMfma) {
-            f4 xa[2][KS];
+// Scan database rows [r0, r1) for the wavefront's 64 queries; lanes with act
+// push their values into top.
+template <int KS, int C>
+__device__ __forceinline__ void scan_rows(const f4 (&qf)[4][KS], const float* X, int64_t ldx,
+                                          const float* xn, int n, int d, int r0, int r1, bool act,
+                                          TopC<C>& top, float* tb, int lane) {
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    f4 xa[2][KS];
+    load_xfrag<KS>(xa, X, ldx, n, d, r0, c16, g);
+    for (int base = r0; base < r1; base += kRowsMfma) {
+        f4 acc[2][4];
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                int row = base + 16 * rb + c16;
-                row = row < a.n ? row : a.n - 1;
-                const float* xp = a.X + (int64_t)row * a.ldx;
+        for (int rb = 0; rb < 2; ++rb) {
+            f4 nv;
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const int f = 16 * s + 4 * g;
-                    f4 v = {0.f, 0.f, 0.f, 0.f};
-                    if (f < a.d) v = *(const f4*)(xp + f);
-                    xa[rb][s] = v;
-                }
-            }
-            f4 acc[2][4];
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                f4 nv;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int row = base + 16 * rb + 4 * g + i;
-                    nv[i] = row < r1 ? a.xn[row] : RBC_INF;
-                }
-#pragma unroll
-                for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = nv;
+            for (int i = 0; i < 4; ++i) {
+                const int row = base + 16 * rb + 4 * g + i;
+                nv[i] = row < r1 ? xn[row] : RBC_INF;
             }
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
+            for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = nv;
+        }
+        f4 xb[2][KS];
+        const int next = base + kRowsMfma;
+        load_xfrag<KS>(xb, X, ldx, n, d, next < r1 ? next : base, c16, g);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+        for (int s = 0; s < KS; ++s) {
 #pragma unroll
-                    for (int rb = 0; rb < 2; ++rb) {
+            for (int j = 0; j < 4; ++j) {
 #pragma unroll
-                        for (int qb = 0; qb < 4; ++qb) {
-                            acc[rb][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                xa[rb][s][j], qf[qb][s][j], acc[rb][qb], 0, 0, 0);
-                        }
+                for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+                    for (int qb = 0; qb < 4; ++qb) {
+                        acc[rb][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            xa[rb][s][j], qf[qb][s][j], acc[rb][qb], 0, 0, 0);
                     }
                 }
             }
-            // transpose: element (query 16 qb + c16, row 16 rb + 4 g + i)
-            wave_lds_sync();
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int qb = 0; qb < 4; ++qb)
-                    *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
-            wave_lds_sync();
-            f4 vals[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) vals[t] = *(const f4*)(tb + lane * kTStride + 4 * t);
-            if (act) {
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
-            }
         }
-    });
-
-    if (qvalid) {
-        const int64_t off = ((int64_t)split * a.m + myslot) * C;
-        top.store(a.pval + off, a.pidx + off);
+        // transpose: element (query 16 qb + c16, row 16 rb + 4 g + i)
+        wave_lds_sync();
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+                *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
+        wave_lds_sync();
+        f4 vals[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) vals[t] = *(const f4*)(tb + lane * kTStride + 4 * t);
+        if (act) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) xa[rb][s] = xb[rb][s];
     }
-    if (GROUPED && a.stats && lane == 0 && pairs) atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)pairs);
 }
 
 template <int KS, int C>
-static hipError_t launch_c(bool grouped, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (grouped)
-        hipLaunchKernelGGL((tile_l2_mfma<KS, C, true>), grid, dim3(256), 0, st, a);
+__global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    const int slot0 = blockIdx.x * kTileQ + wave * kWave;
+
+    f4 qf[4][KS];
+    int qrow[4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+        const int slot = slot0 + 16 * qb + c16;
+        qrow[qb] = slot < a.m ? slot : a.m - 1;
+    }
+    load_qfrag<KS>(qf, a.Q, a.ldq, a.d, qrow, g);
+
+    const int myslot = slot0 + lane;
+    TopC<C> top;
+    top.init();
+    const int64_t r0 = (int64_t)blockIdx.y * a.rps;
+    const int64_t r1 = r0 + a.rps < a.n ? r0 + a.rps : a.n;
+    if (r0 < r1)
+        scan_rows<KS, C>(qf, a.X, a.ldx, a.xn, a.n, a.d, (int)r0, (int)r1, myslot < a.m, top,
+                         tbuf[wave], lane);
+    if (myslot < a.m) {
+        const int64_t off = ((int64_t)blockIdx.y * a.m + myslot) * C;
+        top.store(a.pval + off, a.pidx + off);
+    }
+}
+
+// Exact RBC stage 2: persistent workgroups take (representative, query chunk)
+// items from the queue until it is empty.
+template <int KS, int C>
+__global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_items(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
+    __shared__ int s_item;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    const int total = *a.item_total;
+
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(a.item_queue, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= total) break;
+        const int r = item_rep(a, item);
+        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kTileQ + wave * kWave;
+        const int q_end = a.roff[r + 1];
+        if (q_begin >= q_end) continue;  // uniform per wavefront; no barrier before the next item
+
+        f4 qf[4][KS];
+        int qrow[4];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+            const int p = q_begin + 16 * qb + c16;
+            qrow[qb] = a.qlist[p < q_end ? p : q_end - 1];
+        }
+        load_qfrag<KS>(qf, a.Q, a.ldq, a.d, qrow, g);
+
+        const int p = q_begin + lane;
+        const bool valid = p < q_end;
+        const int q = a.qlist[valid ? p : q_end - 1];
+        TopC<C> top;
+        top.seed(a.tau[q]);
+        scan_rows<KS, C>(qf, a.X, a.ldx, a.xn, a.n, a.d, a.list_off[r], a.list_off[r + 1], valid,
+                         top, tbuf[wave], lane);
+        if (valid) {
+            const int64_t pair = (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r];
+            top.store(a.pval + pair * C, a.pidx + pair * C);
+        }
+        if (a.stats && lane == 0) {
+            const int nq = q_end - q_begin < kWave ? q_end - q_begin : kWave;
+            atomicAdd((unsigned long long*)&a.stats[2],
+                      (unsigned long long)nq * (a.list_off[r + 1] - a.list_off[r]));
+        }
+    }
+}
+
+template <int KS, int C>
+static hipError_t launch_c(bool items, dim3 grid, const TileArgs& a, hipStream_t st) {
+    if (items)
+        hipLaunchKernelGGL((tile_l2_mfma_items<KS, C>), grid, dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((tile_l2_mfma<KS, C, false>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((tile_l2_mfma<KS, C>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 // This file is compiled once per slab count RBC_KS (1..8); each object holds
 // that slab count's kernels for every shortlist length.
-hipError_t RBC_CAT(launch_tile_mfma_ks, RBC_KS)(int c, bool grouped, dim3 grid,
+hipError_t RBC_CAT(launch_tile_mfma_ks, RBC_KS)(int c, bool items, dim3 grid,
                                                 const TileArgs& a, hipStream_t st) {
     switch (c) {
-        case 4: return launch_c<RBC_KS, 4>(grouped, grid, a, st);
-        case 8: return launch_c<RBC_KS, 8>(grouped, grid, a, st);
-        case 16: return launch_c<RBC_KS, 16>(grouped, grid, a, st);
-        case 32: return launch_c<RBC_KS, 32>(grouped, grid, a, st);
-        case 64: return launch_c<RBC_KS, 64>(grouped, grid, a, st);
+        case 4: return launch_c<RBC_KS, 4>(items, grid, a, st);
+        case 8: return launch_c<RBC_KS, 8>(items, grid, a, st);
+        case 16: return launch_c<RBC_KS, 16>(items, grid, a, st);
+        case 32: return launch_c<RBC_KS, 32>(items, grid, a, st);
+        case 64: return launch_c<RBC_KS, 64>(items, grid, a, st);
     }
     return hipErrorInvalidValue;
 }

@@ -15,106 +15,138 @@
 
 namespace rbc {
 
-template <int METRIC, int KS, int C, bool GROUPED>
-__global__ __launch_bounds__(256, 2) void tile_valu(TileArgs a) {
-    constexpr int F4 = 4 * KS;  // float4 per staged row
-    __shared__ f4 xs[kRowsValu * F4];
-
+// Scan database rows [r0, r1): the workgroup stages 32 rows at a time, every
+// lane with act scores them against its query.  Called by all 256 threads.
+template <int METRIC, int KS, int C>
+__device__ __forceinline__ void valu_scan(const f4 (&q)[4 * KS], const float* X, int64_t ldx,
+                                          int d, int r0, int r1, bool act, TopC<C>& top,
+                                          f4* xs) {
+    constexpr int F4 = 4 * KS;
     const int tid = threadIdx.x;
-    const int qblk = blockIdx.x;
-    const int split = blockIdx.y;
-    const int myslot = qblk * kTileQ + tid;
-    const bool qvalid = myslot < a.m;
-    const int qs = qvalid ? myslot : a.m - 1;
-    const int myrow = a.qmap ? a.qmap[qs] : qs;
-
-    f4 q[F4];
-    {
-        const float* qp = a.Q + (int64_t)myrow * a.ldq;
-#pragma unroll
-        for (int j = 0; j < F4; ++j) {
+    for (int base = r0; base < r1; base += kRowsValu) {
+        __syncthreads();
+        for (int e = tid; e < kRowsValu * F4; e += 256) {
+            const int rr = e / F4, cc = e - rr * F4;
+            const int row = base + rr;
             f4 v = {0.f, 0.f, 0.f, 0.f};
-            if (4 * j < a.d) v = *(const f4*)(qp + 4 * j);
-            q[j] = v;
+            if (row < r1 && 4 * cc < d) v = *(const f4*)(X + (int64_t)row * ldx + 4 * cc);
+            xs[e] = v;
+        }
+        __syncthreads();
+        if (act) {
+            const int nrow = r1 - base < kRowsValu ? r1 - base : kRowsValu;
+            for (int t = 0; t < nrow; ++t) {
+                f4 s = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < F4; ++j) {
+                    const f4 df = q[j] - xs[t * F4 + j];
+                    if (METRIC == 0) {
+                        s = df * df + s;
+                    } else {
+                        s[0] += __builtin_fabsf(df[0]);
+                        s[1] += __builtin_fabsf(df[1]);
+                        s[2] += __builtin_fabsf(df[2]);
+                        s[3] += __builtin_fabsf(df[3]);
+                    }
+                }
+                top.push((s[0] + s[1]) + (s[2] + s[3]), base + t);
+            }
         }
     }
+}
 
+template <int KS>
+__device__ __forceinline__ void valu_load_q(f4 (&q)[4 * KS], const float* Q, int64_t ldq, int d,
+                                            int row) {
+    const float* qp = Q + (int64_t)row * ldq;
+#pragma unroll
+    for (int j = 0; j < 4 * KS; ++j) {
+        f4 v = {0.f, 0.f, 0.f, 0.f};
+        if (4 * j < d) v = *(const f4*)(qp + 4 * j);
+        q[j] = v;
+    }
+}
+
+template <int METRIC, int KS, int C>
+__global__ __launch_bounds__(256, 2) void tile_valu(TileArgs a) {
+    __shared__ f4 xs[kRowsValu * 4 * KS];
+    const int myslot = blockIdx.x * kTileQ + threadIdx.x;
+    const bool qvalid = myslot < a.m;
+    f4 q[4 * KS];
+    valu_load_q<KS>(q, a.Q, a.ldq, a.d, qvalid ? myslot : a.m - 1);
     TopC<C> top;
     top.init();
-    int64_t pairs = 0;
-
-    for_each_segment(a, qblk, split, [&](int32_t r0, int32_t r1, int32_t rep) {
-        bool act = qvalid;
-        if (GROUPED) act = act && a.keep[(int64_t)myrow * a.n_r + rep] != 0;
-        if (GROUPED) {
-            const int n_act = __syncthreads_count(act);
-            if (n_act == 0) return;  // uniform: nobody in the block kept this list
-            if (tid == 0) pairs += (int64_t)n_act * (r1 - r0);
-        }
-        for (int32_t base = r0; base < r1; base += kRowsValu) {
-            __syncthreads();
-            for (int e = tid; e < kRowsValu * F4; e += 256) {
-                const int rr = e / F4, cc = e - rr * F4;
-                const int row = base + rr;
-                f4 v = {0.f, 0.f, 0.f, 0.f};
-                if (row < r1 && 4 * cc < a.d) v = *(const f4*)(a.X + (int64_t)row * a.ldx + 4 * cc);
-                xs[e] = v;
-            }
-            __syncthreads();
-            if (act) {
-                const int nrow = r1 - base < kRowsValu ? r1 - base : kRowsValu;
-                for (int t = 0; t < nrow; ++t) {
-                    f4 s = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int j = 0; j < F4; ++j) {
-                        const f4 df = q[j] - xs[t * F4 + j];
-                        if (METRIC == 0) {
-                            s = df * df + s;
-                        } else {
-                            s[0] += __builtin_fabsf(df[0]);
-                            s[1] += __builtin_fabsf(df[1]);
-                            s[2] += __builtin_fabsf(df[2]);
-                            s[3] += __builtin_fabsf(df[3]);
-                        }
-                    }
-                    top.push((s[0] + s[1]) + (s[2] + s[3]), base + t);
-                }
-            }
-        }
-    });
-
+    const int64_t r0 = (int64_t)blockIdx.y * a.rps;
+    const int64_t r1 = r0 + a.rps < a.n ? r0 + a.rps : a.n;
+    if (r0 < r1) valu_scan<METRIC, KS, C>(q, a.X, a.ldx, a.d, (int)r0, (int)r1, qvalid, top, xs);
     if (qvalid) {
-        const int64_t off = ((int64_t)split * a.m + myslot) * C;
+        const int64_t off = ((int64_t)blockIdx.y * a.m + myslot) * C;
         top.store(a.pval + off, a.pidx + off);
     }
-    if (GROUPED && a.stats && tid == 0 && pairs) atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)pairs);
+}
+
+// Exact RBC stage 2 on the vector ALUs: persistent workgroups take
+// (representative, 256-query chunk) items from the queue.
+template <int METRIC, int KS, int C>
+__global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
+    __shared__ f4 xs[kRowsValu * 4 * KS];
+    __shared__ int s_item;
+    const int total = *a.item_total;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(a.item_queue, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= total) break;
+        const int r = item_rep(a, item);
+        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kTileQ;
+        const int q_end = a.roff[r + 1];
+        const int p = q_begin + (int)threadIdx.x;
+        const bool valid = p < q_end;
+        const int q = a.qlist[valid ? p : q_end - 1];
+        f4 qv[4 * KS];
+        valu_load_q<KS>(qv, a.Q, a.ldq, a.d, q);
+        TopC<C> top;
+        top.seed(a.tau[q]);
+        valu_scan<METRIC, KS, C>(qv, a.X, a.ldx, a.d, a.list_off[r], a.list_off[r + 1], valid, top,
+                                 xs);
+        if (valid) {
+            const int64_t pair = (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r];
+            top.store(a.pval + pair * C, a.pidx + pair * C);
+        }
+        if (a.stats && threadIdx.x == 0) {
+            const int nq = q_end - q_begin < kTileQ ? q_end - q_begin : kTileQ;
+            atomicAdd((unsigned long long*)&a.stats[2],
+                      (unsigned long long)nq * (a.list_off[r + 1] - a.list_off[r]));
+        }
+    }
 }
 
 template <int METRIC, int C>
-static hipError_t launch_c(bool grouped, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (grouped)
-        hipLaunchKernelGGL((tile_valu<METRIC, RBC_KS, C, true>), grid, dim3(256), 0, st, a);
+static hipError_t launch_c(bool items, dim3 grid, const TileArgs& a, hipStream_t st) {
+    if (items)
+        hipLaunchKernelGGL((tile_valu_items<METRIC, RBC_KS, C>), grid, dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((tile_valu<METRIC, RBC_KS, C, false>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((tile_valu<METRIC, RBC_KS, C>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 template <int METRIC>
-static hipError_t launch_m(int c, bool grouped, dim3 grid, const TileArgs& a, hipStream_t st) {
+static hipError_t launch_m(int c, bool items, dim3 grid, const TileArgs& a, hipStream_t st) {
     switch (c) {
-        case 4: return launch_c<METRIC, 4>(grouped, grid, a, st);
-        case 8: return launch_c<METRIC, 8>(grouped, grid, a, st);
-        case 16: return launch_c<METRIC, 16>(grouped, grid, a, st);
-        case 32: return launch_c<METRIC, 32>(grouped, grid, a, st);
-        case 64: return launch_c<METRIC, 64>(grouped, grid, a, st);
+        case 4: return launch_c<METRIC, 4>(items, grid, a, st);
+        case 8: return launch_c<METRIC, 8>(items, grid, a, st);
+        case 16: return launch_c<METRIC, 16>(items, grid, a, st);
+        case 32: return launch_c<METRIC, 32>(items, grid, a, st);
+        case 64: return launch_c<METRIC, 64>(items, grid, a, st);
     }
     return hipErrorInvalidValue;
 }
 
 // Compiled once per slab count RBC_KS (1..8).
-hipError_t RBC_CAT(launch_tile_valu_ks, RBC_KS)(int metric, int c, bool grouped, dim3 grid,
+hipError_t RBC_CAT(launch_tile_valu_ks, RBC_KS)(int metric, int c, bool items, dim3 grid,
                                                 const TileArgs& a, hipStream_t st) {
-    return metric == 0 ? launch_m<0>(c, grouped, grid, a, st) : launch_m<1>(c, grouped, grid, a, st);
+    return metric == 0 ? launch_m<0>(c, items, grid, a, st) : launch_m<1>(c, items, grid, a, st);
 }
 
 }  // namespace rbc

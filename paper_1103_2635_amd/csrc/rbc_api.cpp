@@ -95,116 +95,115 @@ void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
     w->pidx = cv.take<int32_t>((int64_t)p.nsplit * m * p.c);
 }
 
-// The launch sequence shared by bf_search and the RBC paths: tile over the
-// database rows (BF mode or grouped mode), finalize, exhaustive fallback.
-int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_t* qmap,
-           const float* X, int64_t n, int64_t ldx, const float* xn, const uint32_t* xmax_bits,
-           const int64_t* id_map, const GroupedArgs* grp, int64_t* out_idx, float* out_dist,
-           BfWork& w, int64_t* stats, hipStream_t st) {
+// The launch sequence of BF(Q, X) (bf_search and the RBC build): tile over
+// the database rows, finalize, exhaustive fallback.  xn / xmax_bits may be
+// given (precomputed norms of X), id_map maps rows of X to reported ids.
+int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
+           int64_t ldx, const float* xn, const uint32_t* xmax_bits, const int64_t* id_map,
+           int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st) {
     int32_t* fb_count = w.counters;
+    int rc;
     if (p.path == kPathExact) {
-        if (qmap) return set_err(RBC_EUNSUPPORTED, "exhaustive path with a query map");
-        int rc = hip_status(launch_iota_i32(w.fb_list, (int32_t)m, st), "iota");
-        if (rc) return rc;
-        rc = hip_status(launch_set_count(fb_count, (int32_t)m, st), "set_count");
-        if (rc) return rc;
-    } else {
-        const float* Qk = Q;
-        int64_t ldqk = ldq;
-        const float* Xk = X;
-        int64_t ldxk = ldx;
-        int rc;
-        if (p.repack_q) {
-            rc = hip_status(launch_repack(Q, m, ldq, p.d, w.Qp, p.ldp, st), "repack Q");
-            if (rc) return rc;
-            Qk = w.Qp;
-            ldqk = p.ldp;
-        }
-        if (p.repack_x) {
-            rc = hip_status(launch_repack(X, n, ldx, p.d, w.Xp, p.ldp, st), "repack X");
-            if (rc) return rc;
-            Xk = w.Xp;
-            ldxk = p.ldp;
-        }
-        rc = hip_status(launch_fill_i32(w.counters, 4, 0, st), "clear counters");
-        if (rc) return rc;
-        const uint32_t* xmaxp = xmax_bits;
-        if (p.path == kPathMfma) {
-            rc = hip_status(launch_row_norms(Qk, m, ldqk, p.d, qmap, w.qn, nullptr, st), "norms Q");
-            if (rc) return rc;
-            if (xn == nullptr) {
-                uint32_t* xm = (uint32_t*)(w.counters + 1);
-                rc = hip_status(launch_row_norms(Xk, n, ldxk, p.d, nullptr, w.xn, xm, st), "norms X");
-                if (rc) return rc;
-                xn = w.xn;
-                xmaxp = xm;
-            }
-        }
-        TileArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.Q = Qk;
-        a.ldq = ldqk;
-        a.m = (int32_t)m;
-        a.qmap = qmap;
-        a.X = Xk;
-        a.ldx = ldxk;
-        a.n = (int32_t)n;
-        a.d = p.d;
-        a.xn = xn;
-        a.rps = p.rps;
-        a.nsplit = p.nsplit;
-        if (grp) {
-            a.blk_reps = grp->blk_reps;
-            a.blk_cnt = grp->blk_cnt;
-            a.blk_pre = grp->blk_pre;
-            a.list_off = grp->list_off;
-            a.keep = grp->keep;
-            a.n_r = grp->n_r;
-        }
-        a.pval = w.pval;
-        a.pidx = w.pidx;
-        a.stats = stats;
-        const dim3 grid(p.nqblk, p.nsplit);
-        {
-            KernelTimer kt(grp ? "tile_grouped" : "tile", st);
-            if (p.path == kPathMfma)
-                rc = hip_status(launch_tile_mfma(p.ks, p.c, grp != nullptr, grid, a, st),
-                                "tile (mfma)");
-            else
-                rc = hip_status(launch_tile_valu(p.metric, p.ks, p.c, grp != nullptr, grid, a, st),
-                                "tile (valu)");
-        }
-        if (rc) return rc;
-
-        FinArgs f;
-        std::memset(&f, 0, sizeof(f));
-        f.Q = Qk;
-        f.ldq = ldqk;
-        f.m = (int32_t)m;
-        f.qmap = qmap;
-        f.X = Xk;
-        f.ldx = ldxk;
-        f.d = p.d;
-        f.metric = p.metric;
-        f.approx_mode = p.path == kPathMfma ? 0 : 1;
-        f.pval = w.pval;
-        f.pidx = w.pidx;
-        f.nsplit = p.nsplit;
-        f.k = p.k;
-        f.qn = w.qn;
-        f.xmax_bits = xmaxp;
-        f.id_map = id_map;
-        f.out_idx = out_idx;
-        f.out_dist = out_dist;
-        f.fb_list = w.fb_list;
-        f.fb_count = fb_count;
-        f.stats = stats;
-        {
-            KernelTimer kt("finalize", st);
-            rc = hip_status(launch_finalize(p.c, f, st), "finalize");
-        }
-        if (rc) return rc;
+        if ((rc = hip_status(launch_iota_i32(w.fb_list, (int32_t)m, st), "iota"))) return rc;
+        if ((rc = hip_status(launch_set_count(fb_count, (int32_t)m, st), "set_count"))) return rc;
+        return run_fallback(p, Q, m, ldq, X, n, ldx, id_map, out_idx, out_dist, w, st);
     }
+    const float* Qk = Q;
+    int64_t ldqk = ldq;
+    const float* Xk = X;
+    int64_t ldxk = ldx;
+    if (p.repack_q) {
+        if ((rc = hip_status(launch_repack(Q, m, ldq, p.d, w.Qp, p.ldp, st), "repack Q"))) return rc;
+        Qk = w.Qp;
+        ldqk = p.ldp;
+    }
+    if (p.repack_x) {
+        if ((rc = hip_status(launch_repack(X, n, ldx, p.d, w.Xp, p.ldp, st), "repack X"))) return rc;
+        Xk = w.Xp;
+        ldxk = p.ldp;
+    }
+    if ((rc = hip_status(launch_fill_i32(w.counters, 4, 0, st), "clear counters"))) return rc;
+    const uint32_t* xmaxp = xmax_bits;
+    if (p.path == kPathMfma) {
+        if ((rc = hip_status(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.qn, nullptr, st),
+                             "norms Q")))
+            return rc;
+        if (xn == nullptr) {
+            uint32_t* xm = (uint32_t*)(w.counters + 1);
+            if ((rc = hip_status(launch_row_norms(Xk, n, ldxk, p.d, nullptr, w.xn, xm, st),
+                                 "norms X")))
+                return rc;
+            xn = w.xn;
+            xmaxp = xm;
+        }
+    }
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = Qk;
+    a.ldq = ldqk;
+    a.m = (int32_t)m;
+    a.X = Xk;
+    a.ldx = ldxk;
+    a.n = (int32_t)n;
+    a.d = p.d;
+    a.xn = xn;
+    a.rps = p.rps;
+    a.nsplit = p.nsplit;
+    a.pval = w.pval;
+    a.pidx = w.pidx;
+    a.stats = stats;
+    {
+        KernelTimer kt("tile", st);
+        const dim3 grid(p.nqblk, p.nsplit);
+        rc = p.path == kPathMfma
+                 ? hip_status(launch_tile_mfma(p.ks, p.c, false, grid, a, st), "tile (mfma)")
+                 : hip_status(launch_tile_valu(p.metric, p.ks, p.c, false, grid, a, st),
+                              "tile (valu)");
+    }
+    if (rc) return rc;
+    FinArgs f = fin_args(p, Qk, m, ldqk, Xk, ldxk, xmaxp, id_map, out_idx, out_dist, w, stats);
+    f.nsplit = p.nsplit;
+    if ((rc = run_finalize(p, f, st))) return rc;
+    return run_fallback(p, Q, m, ldq, X, n, ldx, id_map, out_idx, out_dist, w, st);
+}
+
+FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, const float* Xk,
+                 int64_t ldxk, const uint32_t* xmax_bits, const int64_t* id_map,
+                 int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats) {
+    FinArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.Q = Qk;
+    f.ldq = ldqk;
+    f.m = (int32_t)m;
+    f.X = Xk;
+    f.ldx = ldxk;
+    f.d = p.d;
+    f.metric = p.metric;
+    f.approx_mode = p.path == kPathMfma ? 0 : 1;
+    f.pval = w.pval;
+    f.pidx = w.pidx;
+    f.k = p.k;
+    f.qn = w.qn;
+    f.xmax_bits = xmax_bits;
+    f.id_map = id_map;
+    f.out_idx = out_idx;
+    f.out_dist = out_dist;
+    f.fb_list = w.fb_list;
+    f.fb_count = w.counters;
+    f.stats = stats;
+    return f;
+}
+
+int run_finalize(const BfPlan& p, const FinArgs& f, hipStream_t st) {
+    KernelTimer kt("finalize", st);
+    return hip_status(launch_finalize(p.c, f, st), "finalize");
+}
+
+// Exhaustive float64 search of the queries listed in w.fb_list (count in
+// w.counters[0]) over X, on the original (not repacked) inputs.
+int run_fallback(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X,
+                 int64_t n, int64_t ldx, const int64_t* id_map, int64_t* out_idx,
+                 float* out_dist, BfWork& w, hipStream_t st) {
     ExactArgs e;
     std::memset(&e, 0, sizeof(e));
     e.Q = Q;
@@ -216,11 +215,11 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_
     e.metric = p.metric;
     e.k = p.k;
     e.list = w.fb_list;
-    e.count = fb_count;
+    e.count = w.counters;
     e.id_map = id_map;
     e.out_idx = out_idx;
     e.out_dist = out_dist;
-    int grid = p.path == kPathExact ? (int)std::min<int64_t>(m, 2048) : kFallbackBlocks;
+    const int grid = p.path == kPathExact ? (int)std::min<int64_t>(m, 2048) : kFallbackBlocks;
     KernelTimer kt("fallback", st);
     return hip_status(launch_exact(e, grid, st), "exact fallback");
 }
@@ -288,9 +287,8 @@ int bf_search(const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
         if (!workspace || ws_bytes < cv.size())
             return set_err(RBC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu needed",
                            ws_bytes, cv.size());
-        return run_bf(p, Q, m, ldq, nullptr, X, n, ldx, nullptr, nullptr, nullptr, nullptr,
-                      out_idx, out_dist, w, opts ? opts->dev_stats : nullptr,
-                      (hipStream_t)hip_stream);
+        return run_bf(p, Q, m, ldq, X, n, ldx, nullptr, nullptr, nullptr, out_idx, out_dist, w,
+                      opts ? opts->dev_stats : nullptr, (hipStream_t)hip_stream);
     } catch (...) {
         return set_err(RBC_EHIP, "unexpected exception");
     }

@@ -22,19 +22,19 @@ constexpr int kExactKCap = 1024;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// One tile launch.  BF mode (blk_reps == nullptr): split s scans database rows
-// [s * rps, min(n, (s + 1) * rps)).  Grouped mode (exact RBC stage 2): the
-// 256-slot query block b owns a list of representatives blk_reps[b * n_r + j],
-// j < blk_cnt[b], whose lists L_r are the row ranges [list_off[r],
-// list_off[r + 1]) of X; blk_pre[b * (n_r + 1) + j] is the number of rows
-// before the j-th of them, and split s scans rows [s * U / S, (s + 1) * U / S)
-// of that concatenation (U = blk_pre[b * (n_r + 1) + blk_cnt[b]]).  A query
-// only scores lists it kept: keep[qrow * n_r + r] != 0.
+// One tile launch.  BF mode: grid (query blocks of 256, database splits);
+// split s scans database rows [s * rps, min(n, (s + 1) * rps)) and leaves a
+// partial shortlist per query at pval[(s * m + q) * C].
+// Item mode (exact RBC stage 2): a persistent grid takes items from a queue;
+// item i belongs to the representative r with ioff[r] <= i < ioff[r + 1] and
+// covers queries qlist[roff[r] + (i - ioff[r]) * 256 ...] (at most 256, all
+// of which kept L_r); those queries scan the rows [list_off[r],
+// list_off[r + 1]) of X, starting from the shortlist threshold tau[q], and
+// leave their partial shortlist at pair qoff[q] + lrank[q * n_r + r].
 struct TileArgs {
     const float* Q;
     int64_t ldq;
-    int32_t m;             // query slots
-    const int32_t* qmap;   // slot -> row of Q (nullptr: identity)
+    int32_t m;
     const float* X;
     int64_t ldx;
     int32_t n;
@@ -42,14 +42,18 @@ struct TileArgs {
     const float* xn;       // squared norms of X rows (MFMA path)
     int32_t rps;
     int32_t nsplit;
-    const int32_t* blk_reps;
-    const int32_t* blk_cnt;
-    const int64_t* blk_pre;
+    const int32_t* item_total;
+    int32_t* item_queue;
+    const int32_t* ioff;
+    const int32_t* roff;
+    const int32_t* qlist;
     const int32_t* list_off;
-    const uint8_t* keep;
+    const int32_t* lrank;
+    const int32_t* qoff;
+    const float* tau;
     int32_t n_r;
-    float* pval;           // [nsplit][m][C] partial shortlist values
-    int32_t* pidx;         // [nsplit][m][C] partial shortlist rows (-1 = empty)
+    float* pval;           // partial shortlist values
+    int32_t* pidx;         // partial shortlist rows (-1 = no row)
     int64_t* stats;        // optional device counters
 };
 
@@ -59,7 +63,6 @@ struct FinArgs {
     const float* Q;
     int64_t ldq;
     int32_t m;
-    const int32_t* qmap;
     const float* X;
     int64_t ldx;
     int32_t d;
@@ -67,9 +70,11 @@ struct FinArgs {
     int32_t approx_mode;   // 0: values are ||x||^2 - 2 q.x (MFMA); 1: direct d^2 (l2) or rho (l1)
     const float* pval;
     const int32_t* pidx;
-    int32_t nsplit;
+    int32_t nsplit;        // BF mode: lists of query q at (s * m + q) * C, s < nsplit
+    const int32_t* qoff;   // pair mode (non-null): lists qoff[q] .. qoff[q] + npairs[q] - 1
+    const int32_t* npairs;
     int32_t k;
-    const float* qn;       // squared query norms by slot (approx_mode 0)
+    const float* qn;       // squared query norms (approx_mode 0)
     const uint32_t* xmax_bits;  // largest database row norm (float bits, approx_mode 0)
     const int64_t* id_map; // row of X -> reported id (nullptr: identity)
     int64_t* out_idx;      // [rows of Q][k]
@@ -105,17 +110,17 @@ hipError_t launch_repack(const float* A, int64_t rows, int64_t lda, int32_t d, f
 hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d,
                             const int32_t* rowmap, float* out, uint32_t* maxbits,
                             hipStream_t st);
-hipError_t launch_tile_mfma(int ks, int c, bool grouped, dim3 grid, const TileArgs& a,
+hipError_t launch_tile_mfma(int ks, int c, bool items, dim3 grid, const TileArgs& a,
                             hipStream_t st);
-hipError_t launch_tile_valu(int metric, int ks, int c, bool grouped, dim3 grid,
+hipError_t launch_tile_valu(int metric, int ks, int c, bool items, dim3 grid,
                             const TileArgs& a, hipStream_t st);
 
 #define RBC_CAT_(a, b) a##b
 #define RBC_CAT(a, b) RBC_CAT_(a, b)
 #define RBC_DECL_KS(n)                                                                     \
-    hipError_t launch_tile_mfma_ks##n(int c, bool grouped, dim3 grid, const TileArgs& a,   \
+    hipError_t launch_tile_mfma_ks##n(int c, bool items, dim3 grid, const TileArgs& a,     \
                                       hipStream_t st);                                     \
-    hipError_t launch_tile_valu_ks##n(int metric, int c, bool grouped, dim3 grid,          \
+    hipError_t launch_tile_valu_ks##n(int metric, int c, bool items, dim3 grid,            \
                                       const TileArgs& a, hipStream_t st);
 RBC_DECL_KS(1)
 RBC_DECL_KS(2)

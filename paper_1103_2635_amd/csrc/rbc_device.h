@@ -46,6 +46,15 @@ struct TopC {
         }
     }
 
+    // Start from a known bound: only values below t can enter.
+    __device__ __forceinline__ void seed(float t) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            v[j] = t;
+            i[j] = -1;
+        }
+    }
+
     __device__ __forceinline__ float worst() const { return v[C - 1]; }
 
     // Insert (x, id) given x < v[C - 1]; the last entry drops out.
@@ -77,38 +86,15 @@ struct TopC {
     }
 };
 
-// Calls body(r0, r1, rep) for every row range this (query block, split)
-// workgroup scans.  rep = -1 in BF mode.  Uniform across the workgroup.
-template <typename Body>
-__device__ __forceinline__ void for_each_segment(const TileArgs& a, int qblk, int split,
-                                                 Body&& body) {
-    if (a.blk_reps == nullptr) {
-        const int64_t r0 = (int64_t)split * a.rps;
-        const int64_t r1 = r0 + a.rps < a.n ? r0 + a.rps : a.n;
-        if (r0 < r1) body((int32_t)r0, (int32_t)r1, -1);
-        return;
-    }
-    const int32_t cnt = a.blk_cnt[qblk];
-    const int64_t* pre = a.blk_pre + (int64_t)qblk * (a.n_r + 1);
-    const int32_t* reps = a.blk_reps + (int64_t)qblk * a.n_r;
-    const int64_t total = pre[cnt];
-    const int64_t start = total * split / a.nsplit;
-    const int64_t end = total * (split + 1) / a.nsplit;
-    if (start >= end) return;
-    // first j with pre[j + 1] > start
-    int32_t lo = 0, hi = cnt - 1;
+// Representative of work item `item` (item mode): the last r with
+// ioff[r] <= item (representatives without items have ioff[r] == ioff[r + 1]).
+__device__ __forceinline__ int item_rep(const TileArgs& a, int item) {
+    int lo = 0, hi = a.n_r - 1;
     while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (pre[mid + 1] > start) hi = mid; else lo = mid + 1;
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.ioff[mid] <= item) lo = mid; else hi = mid - 1;
     }
-    for (int32_t j = lo; j < cnt && pre[j] < end; ++j) {
-        const int32_t r = reps[j];
-        const int64_t a0 = start > pre[j] ? start : pre[j];
-        const int64_t a1 = end < pre[j + 1] ? end : pre[j + 1];
-        if (a0 >= a1) continue;
-        const int32_t base = a.list_off[r];
-        body(base + (int32_t)(a0 - pre[j]), base + (int32_t)(a1 - pre[j]), r);
-    }
+    return lo;
 }
 
 // Makes this wavefront's LDS writes visible to its own later LDS reads (and

@@ -16,6 +16,7 @@ constexpr int kPathExact = 2;  // exhaustive float64 (k or d beyond the tiles)
 constexpr int kConcurrentBlocks = 512;  // 256 CUs x 2 resident tile workgroups
 constexpr int kMaxSplits = 64;          // one partial list per lane in finalize
 constexpr int kFallbackBlocks = 256;
+constexpr int kItemBlocks = 1024;       // persistent grid of the stage-2 item kernels
 
 int set_err(int status, const char* fmt, ...);
 const char* last_error();
@@ -65,15 +66,6 @@ struct BfWork {
     int32_t* pidx = nullptr;
 };
 
-struct GroupedArgs {
-    const int32_t* blk_reps;
-    const int32_t* blk_cnt;
-    const int64_t* blk_pre;
-    const int32_t* list_off;
-    const uint8_t* keep;
-    int32_t n_r;
-};
-
 // Records a pair of HIP events around a launch when timing is enabled
 // (rbc_timer_enable); the scope is the launch.
 class KernelTimer {
@@ -91,10 +83,16 @@ private:
 int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int32_t metric,
                  int32_t k, const rbc_search_opts* opts, BfPlan* p);
 void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w);
-int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const int32_t* qmap,
-           const float* X, int64_t n, int64_t ldx, const float* xn, const uint32_t* xmax_bits,
-           const int64_t* id_map, const GroupedArgs* grp, int64_t* out_idx, float* out_dist,
-           BfWork& w, int64_t* stats, hipStream_t st);
+int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
+           int64_t ldx, const float* xn, const uint32_t* xmax_bits, const int64_t* id_map,
+           int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st);
+FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, const float* Xk,
+                 int64_t ldxk, const uint32_t* xmax_bits, const int64_t* id_map,
+                 int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats);
+int run_finalize(const BfPlan& p, const FinArgs& f, hipStream_t st);
+int run_fallback(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X,
+                 int64_t n, int64_t ldx, const int64_t* id_map, int64_t* out_idx,
+                 float* out_dist, BfWork& w, hipStream_t st);
 int validate_common(int64_t m, int64_t n, int32_t d, int32_t k, int32_t metric);
 
 }  // namespace rbc

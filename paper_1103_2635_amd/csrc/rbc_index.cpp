@@ -146,8 +146,8 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     if ((rc = s.take(&ws, (int64_t)probe.size()))) return rc;
     Carver cv(ws);
     carve_bf(p, n, n_r, cv, &w);
-    if ((rc = run_bf(p, X, n, ldx, nullptr, ix->R, n_r, ld, nullptr, nullptr, nullptr, nullptr,
-                     own64, ownd, w, nullptr, st)))
+    if ((rc = run_bf(p, X, n, ldx, ix->R, n_r, ld, nullptr, nullptr, nullptr, own64, ownd, w,
+                     nullptr, st)))
         return rc;
     if ((rc = check(launch_narrow(own64, n, owner, st), "owners"))) return rc;
 
@@ -168,33 +168,49 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
 
 struct SearchWork {
     BfWork bf;
-    float* DR = nullptr;
-    uint8_t* keep = nullptr;
-    int32_t* nearest = nullptr;
-    int32_t* qmap = nullptr;
-    int32_t* cnt = nullptr;
-    int32_t* blk_reps = nullptr;
-    int32_t* blk_cnt = nullptr;
-    int64_t* blk_pre = nullptr;
+    float* DR = nullptr;       // stage-1 distances, m x ldd
+    int32_t* lrank = nullptr;  // m x n_r
+    uint8_t* keep_rq = nullptr;  // n_r x m
+    int32_t* npairs = nullptr;   // m
+    int32_t* qoff = nullptr;     // m + 1
+    float* gcup = nullptr;       // m
+    float* tau = nullptr;        // m
+    int32_t* roff = nullptr;     // n_r + 1
+    int32_t* ioff = nullptr;     // n_r + 1
+    int32_t* qlist = nullptr;    // up to m * n_r
 };
 
+int64_t stage1_ld(int64_t nr) { return (nr + 3) / 4 * 4; }
+
 void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, SearchWork* w) {
-    carve_bf(p, m, ix->rows, cv, &w->bf);
-    if (p.path == kPathExact) return;
+    if (p.path == kPathExact) {
+        carve_bf(p, m, ix->rows, cv, &w->bf);
+        return;
+    }
     const int64_t nr = ix->n_r;
-    w->DR = cv.take<float>(m * ((nr + 3) / 4 * 4));
-    w->keep = cv.take<uint8_t>(m * nr);
-    w->nearest = cv.take<int32_t>(m);
-    w->qmap = cv.take<int32_t>(m);
-    w->cnt = cv.take<int32_t>(nr * csort_blocks(m));
-    w->blk_reps = cv.take<int32_t>((int64_t)p.nqblk * nr);
-    w->blk_cnt = cv.take<int32_t>(p.nqblk);
-    w->blk_pre = cv.take<int64_t>((int64_t)p.nqblk * (nr + 1));
+    w->bf.fb_list = cv.take<int32_t>(m);
+    w->bf.counters = cv.take<int32_t>(4);
+    if (p.repack_q) w->bf.Qp = cv.take<float>(m * p.ldp);
+    if (p.path == kPathMfma) w->bf.qn = cv.take<float>(m);
+    w->bf.pval = cv.take<float>(m * nr * p.c);
+    w->bf.pidx = cv.take<int32_t>(m * nr * p.c);
+    w->DR = cv.take<float>(m * stage1_ld(nr));
+    w->lrank = cv.take<int32_t>(m * nr);
+    w->keep_rq = cv.take<uint8_t>(m * nr);
+    w->npairs = cv.take<int32_t>(m);
+    w->qoff = cv.take<int32_t>(m + 1);
+    w->gcup = cv.take<float>(m);
+    w->tau = cv.take<float>(m);
+    w->roff = cv.take<int32_t>(nr + 1);
+    w->ioff = cv.take<int32_t>(nr + 1);
+    w->qlist = cv.take<int32_t>(m * nr);
 }
 
 int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
                 const rbc_search_opts* opts, BfPlan* p) {
     if (ix->mode != RBC_EXACT) return set_err(RBC_EUNSUPPORTED, "one-shot search is not built yet");
+    if ((int64_t)m * ix->n_r >= ((int64_t)1 << 31))
+        return set_err(RBC_EUNSUPPORTED, "m * n_r >= 2^31: split the query batch");
     return make_bf_plan(m > 0 ? m : 1, ix->rows, ix->d, ldq, ix->ld, ix->metric, k, opts, p);
 }
 
@@ -204,6 +220,95 @@ int validate_search(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k) {
     if (rc) return rc;
     if (ldq < ix->d) return set_err(RBC_EINVAL, "ldq smaller than d");
     return RBC_OK;
+}
+
+// Exact search, Sec. 5.2: stage 1 (all representative distances), pruning,
+// work list, grouped persistent stage-2 tile, finalize, fallback.
+int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m, int64_t ldq,
+                 int32_t k, int64_t* out_idx, float* out_dist, SearchWork& w, int64_t* stats,
+                 hipStream_t st) {
+    const int32_t nr = (int32_t)ix->n_r;
+    const double delta = 2.0 * (ix->d + 2) * 5.9604644775390625e-8;
+    const int64_t ldd = stage1_ld(nr);
+    int rc;
+    const float* Qk = Q;
+    int64_t ldqk = ldq;
+    if (p.repack_q) {
+        if ((rc = check(launch_repack(Q, m, ldq, p.d, w.bf.Qp, p.ldp, st), "repack Q"))) return rc;
+        Qk = w.bf.Qp;
+        ldqk = p.ldp;
+    }
+    if ((rc = check(launch_fill_i32(w.bf.counters, 4, 0, st), "clear counters"))) return rc;
+    {
+        KernelTimer kt("stage1", st);
+        if ((rc = check(launch_dist_all(ix->metric, Q, ldq, (int32_t)m, ix->R, ix->ld, nr, ix->d,
+                                        w.DR, ldd, st), "stage 1")))
+            return rc;
+    }
+    {
+        KernelTimer kt("prune", st);
+        if ((rc = check(launch_prune(w.DR, ldd, (int32_t)m, nr, k, p.c, delta, ix->psi,
+                                     ix->list_off, w.lrank, w.keep_rq, w.npairs, w.gcup, stats,
+                                     st), "prune")))
+            return rc;
+    }
+    {
+        KernelTimer kt("worklist", st);
+        if ((rc = check(hipMemcpyAsync(w.qoff, w.npairs, m * sizeof(int32_t),
+                                       hipMemcpyDeviceToDevice, st), "copy counts")))
+            return rc;
+        if ((rc = check(launch_scan_total(w.qoff, m, st), "pair offsets"))) return rc;
+        if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, w.roff, w.ioff, w.qlist, st),
+                        "work list")))
+            return rc;
+        if (p.path == kPathMfma &&
+            (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st),
+                        "norms Q")))
+            return rc;
+        const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
+        if ((rc = check(launch_tau(w.gcup, w.bf.qn, ix->norms_max, (int32_t)m, ix->d, mode, delta,
+                                   w.tau, st), "thresholds")))
+            return rc;
+    }
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = Qk;
+    a.ldq = ldqk;
+    a.m = (int32_t)m;
+    a.X = ix->Xp;
+    a.ldx = ix->ld;
+    a.n = (int32_t)ix->rows;
+    a.d = ix->d;
+    a.xn = ix->xn;
+    a.item_total = w.ioff + nr;
+    a.item_queue = w.bf.counters + 2;
+    a.ioff = w.ioff;
+    a.roff = w.roff;
+    a.qlist = w.qlist;
+    a.list_off = ix->list_off;
+    a.lrank = w.lrank;
+    a.qoff = w.qoff;
+    a.tau = w.tau;
+    a.n_r = nr;
+    a.pval = w.bf.pval;
+    a.pidx = w.bf.pidx;
+    a.stats = stats;
+    {
+        KernelTimer kt("tile_items", st);
+        const dim3 grid(kItemBlocks);
+        rc = p.path == kPathMfma
+                 ? check(launch_tile_mfma(p.ks, p.c, true, grid, a, st), "stage 2 (mfma)")
+                 : check(launch_tile_valu(p.metric, p.ks, p.c, true, grid, a, st),
+                         "stage 2 (valu)");
+        if (rc) return rc;
+    }
+    FinArgs f = fin_args(p, Qk, m, ldqk, ix->Xp, ix->ld, ix->norms_max, ix->ids, out_idx,
+                         out_dist, w.bf, stats);
+    f.qoff = w.qoff;
+    f.npairs = w.npairs;
+    if ((rc = run_finalize(p, f, st))) return rc;
+    return run_fallback(p, Q, m, ldq, ix->Xp, ix->rows, ix->ld, ix->ids, out_idx, out_dist, w.bf,
+                        st);
 }
 
 }  // namespace
@@ -306,41 +411,9 @@ int rbc_search(const rbc_index* ix, const float* Q, int64_t m, int64_t ldq, int3
         hipStream_t st = (hipStream_t)hip_stream;
         int64_t* stats = opts ? opts->dev_stats : nullptr;
         if (p.path == kPathExact)
-            return run_bf(p, Q, m, ldq, nullptr, ix->Xp, ix->rows, ix->ld, nullptr, nullptr,
-                          ix->ids, nullptr, out_idx, out_dist, w.bf, stats, st);
-        const int32_t nr = (int32_t)ix->n_r;
-        const double u = 5.9604644775390625e-8;
-        const double delta = 2.0 * (ix->d + 2) * u;
-        const int64_t ldd = ((int64_t)nr + 3) / 4 * 4;  // row stride of the stage-1 distances
-        {
-            KernelTimer kt("stage1", st);
-            if ((rc = check(launch_dist_all(ix->metric, Q, ldq, (int32_t)m, ix->R, ix->ld, nr,
-                                            ix->d, w.DR, ldd, st), "stage 1")))
-                return rc;
-        }
-        {
-            KernelTimer kt("prune", st);
-            if ((rc = check(launch_prune(w.DR, ldd, (int32_t)m, nr, k, delta, ix->psi,
-                                         ix->list_off, w.keep, w.nearest, stats, st), "prune")))
-                return rc;
-        }
-        {
-            KernelTimer kt("group", st);
-            if ((rc = check(launch_csort(w.nearest, m, nr, w.cnt, w.qmap, nullptr, st), "group")))
-                return rc;
-            if ((rc = check(launch_block_union(w.keep, w.qmap, (int32_t)m, nr, ix->list_off,
-                                               w.blk_reps, w.blk_cnt, w.blk_pre, st), "union")))
-                return rc;
-        }
-        GroupedArgs g;
-        g.blk_reps = w.blk_reps;
-        g.blk_cnt = w.blk_cnt;
-        g.blk_pre = w.blk_pre;
-        g.list_off = ix->list_off;
-        g.keep = w.keep;
-        g.n_r = nr;
-        return run_bf(p, Q, m, ldq, w.qmap, ix->Xp, ix->rows, ix->ld, ix->xn, ix->norms_max,
-                      ix->ids, &g, out_idx, out_dist, w.bf, stats, st);
+            return run_bf(p, Q, m, ldq, ix->Xp, ix->rows, ix->ld, nullptr, nullptr, ix->ids,
+                          out_idx, out_dist, w.bf, stats, st);
+        return search_exact(ix, p, Q, m, ldq, k, out_idx, out_dist, w, stats, st);
     } catch (...) {
         return set_err(RBC_EHIP, "unexpected exception");
     }

@@ -23,11 +23,16 @@ hipError_t launch_psi(const float* X, int64_t ldx, int32_t d, int32_t metric, in
 hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, const float* R,
                            int64_t ldr, int32_t nr, int32_t d, float* DR, int64_t ldd,
                            hipStream_t st);
-hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k,
-                        double delta, const double* psi, const int32_t* list_off, uint8_t* keep,
-                        int32_t* nearest, int64_t* stats, hipStream_t st);
-hipError_t launch_block_union(const uint8_t* keep, const int32_t* qmap, int32_t m, int32_t nr,
-                              const int32_t* list_off, int32_t* blk_reps, int32_t* blk_cnt,
-                              int64_t* blk_pre, hipStream_t st);
+hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
+                        double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
+                        uint8_t* keep_rq, int32_t* nkept, float* gcup, int64_t* stats,
+                        hipStream_t st);
+// roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.
+hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_t* roff,
+                           int32_t* ioff, int32_t* qlist, hipStream_t st);
+// exclusive scan of v[0 .. n), total to v[n]
+hipError_t launch_scan_total(int32_t* v, int64_t n, hipStream_t st);
+hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits, int32_t m,
+                      int32_t d, int32_t mode, double delta, float* tau, hipStream_t st);
 
 }  // namespace rbc
