@@ -24,7 +24,7 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 PER_KS = ["k_tile_mfma.hip", "k_tile_valu.hip"]
-SINGLE = ["k_util.hip", "k_finalize.hip", "k_rbc.hip", "rbc_dispatch.cpp", "rbc_api.cpp",
+SINGLE = ["k_util.hip", "k_finalize.hip", "k_rbc.hip", "k_oneshot.hip", "rbc_dispatch.cpp", "rbc_api.cpp",
           "rbc_index.cpp", "rbc_timer.cpp"]
 
 

@@ -153,7 +153,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             const double qn = a.qn[slot];
             const double xmax = (double)__uint_as_float(*a.xmax_bits);
             const double sq = __builtin_sqrt(qn) + xmax;
-            const double e = 4.0 * (a.d + 2) * u * sq * sq;
+            const double e =
+                tile_exact(a.flags_q, a.flags_x, a.d) ? 0.0 : 4.0 * (a.d + 2) * u * sq * sq;
             const double lo2 = (double)a_c + qn - e;
             lo = lo2 > 0.0 ? __builtin_sqrt(lo2) : 0.0;
         } else if (a.metric == 0) {
@@ -213,6 +214,11 @@ __global__ __launch_bounds__(256) void exact_fp64_kernel(ExactArgs a) {
     for (int f = blockIdx.x; f < count; f += gridDim.x) {
         const int qrow = a.list[f];
         const float* qp = a.Q + (int64_t)qrow * a.ldq;
+        int row0 = 0, row1 = a.n;
+        if (a.qrep) {
+            row0 = a.list_off[a.qrep[qrow]];
+            row1 = a.list_off[a.qrep[qrow] + 1];
+        }
         if (tid == 0) {
             s_kcnt = 0;
             s_bcnt = 0;
@@ -220,9 +226,9 @@ __global__ __launch_bounds__(256) void exact_fp64_kernel(ExactArgs a) {
             s_thr_id = INT64_MAX;
         }
         __syncthreads();
-        for (int base = 0; base < a.n; base += 256) {
+        for (int base = row0; base < row1; base += 256) {
             const int row = base + tid;
-            if (row < a.n) {
+            if (row < row1) {
                 const double r = rho_fp64(qp, a.X + (int64_t)row * a.ldx, a.d, a.metric);
                 const int64_t id = a.id_map ? a.id_map[row] : (int64_t)row;
                 if (before(r, id, s_thr, s_thr_id)) {
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(256) void exact_fp64_kernel(ExactArgs a) {
             }
             __syncthreads();
             const int bcnt = s_bcnt;
-            if (bcnt > kExactBuf - 256 || base + 256 >= a.n) {
+            if (bcnt > kExactBuf - 256 || base + 256 >= row1) {
                 // merge: rank every entry of (top, buffer) by counting the
                 // entries before it; ranks are distinct, keep ranks < k.
                 const int kcnt = s_kcnt;

@@ -47,34 +47,13 @@ hipError_t launch_narrow(const int64_t* in, int64_t n, int32_t* out, hipStream_t
     return hipGetLastError();
 }
 
-// ------------------------------------------------------ stable counting sort
-// Items 0..n-1 with keys in [0, nk) are ordered by (key, item).  Block b of
-// the item range holds items [b * B, (b + 1) * B).  cnt[key * nblk + b] counts
-// block b's items with that key; its exclusive scan in that (key-major) order
-// is where block b's first item of the key goes.
-
-__global__ __launch_bounds__(256) void csort_count_kernel(const int32_t* keys, int64_t n,
-                                                          int32_t nk, int32_t B, int32_t nblk,
-                                                          int32_t* cnt) {
-    extern __shared__ int32_t hist[];
-    const int b = blockIdx.x;
-    for (int r = threadIdx.x; r < nk; r += 256) hist[r] = 0;
-    __syncthreads();
-    const int64_t i0 = (int64_t)b * B;
-    const int64_t i1 = i0 + B < n ? i0 + B : n;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) atomicAdd(&hist[keys[i]], 1);
-    __syncthreads();
-    for (int r = threadIdx.x; r < nk; r += 256) cnt[(int64_t)r * nblk + b] = hist[r];
-}
-
-// In-place exclusive scan of total int32 values by one workgroup of 1024
-// threads (each thread scans a contiguous chunk).
-__global__ __launch_bounds__(1024) void scan_1wg_kernel(int32_t* v, int64_t total) {
+// In-place exclusive scan of v[0 .. n) by one workgroup; v[n] = the total.
+__global__ __launch_bounds__(1024) void scan_total_kernel(int32_t* v, int64_t n) {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
-    const int64_t chunk = (total + 1023) / 1024;
+    const int64_t chunk = (n + 1023) / 1024;
     const int64_t s = t * chunk;
-    const int64_t e = s + chunk < total ? s + chunk : total;
+    const int64_t e = s + chunk < n ? s + chunk : n;
     int64_t acc = 0;
     for (int64_t i = s; i < e; ++i) acc += v[i];
     part[t] = acc;
@@ -91,38 +70,124 @@ __global__ __launch_bounds__(1024) void scan_1wg_kernel(int32_t* v, int64_t tota
         v[i] = (int32_t)run;
         run += x;
     }
+    if (t == 1023) v[n] = (int32_t)part[1023];
 }
 
-// Stable scatter: items of block b are placed in id order; inside a chunk of
-// 256 items an item's rank among equal keys is the number of lower threads
-// holding the same key.
-__global__ __launch_bounds__(256) void csort_scatter_kernel(const int32_t* keys, int64_t n,
-                                                            int32_t nk, int32_t B, int32_t nblk,
-                                                            const int32_t* start, int32_t* perm) {
-    extern __shared__ int32_t run[];
-    __shared__ int32_t ck[256];
+// ------------------------------------------------------ stable counting sort
+// Items 0..n-1 with keys in [0, nk) are ordered by (key, item).  Block b of
+// the item range holds items [b * B, (b + 1) * B) and is handled by one
+// wavefront.  cnt[key * nblk + b] counts block b's items with that key; its
+// exclusive scan in that (key-major) order is where block b's first item of
+// the key goes.
+
+__global__ __launch_bounds__(64) void csort_count_kernel(const int32_t* keys, int64_t n,
+                                                         int32_t nk, int32_t B, int32_t nblk,
+                                                         int32_t* cnt) {
+    extern __shared__ int32_t hist[];
     const int b = blockIdx.x;
-    const int t = threadIdx.x;
-    for (int r = t; r < nk; r += 256) run[r] = start[(int64_t)r * nblk + b];
+    for (int r = threadIdx.x; r < nk; r += 64) hist[r] = 0;
     __syncthreads();
     const int64_t i0 = (int64_t)b * B;
     const int64_t i1 = i0 + B < n ? i0 + B : n;
-    for (int64_t base = i0; base < i1; base += 256) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 64) atomicAdd(&hist[keys[i]], 1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < nk; r += 64) cnt[(int64_t)r * nblk + b] = hist[r];
+}
+
+// Stable scatter: chunks of 64 items in id order; a lane's rank among equal
+// keys of its chunk is the number of lower lanes holding the same key, and
+// the highest such lane advances the running position of the key.
+__global__ __launch_bounds__(64) void csort_scatter_kernel(const int32_t* keys, int64_t n,
+                                                           int32_t nk, int32_t B, int32_t nblk,
+                                                           const int32_t* start, int32_t* perm) {
+    extern __shared__ int32_t run[];
+    const int b = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int r = t; r < nk; r += 64) run[r] = start[(int64_t)r * nblk + b];
+    __syncthreads();
+    const int64_t i0 = (int64_t)b * B;
+    const int64_t i1 = i0 + B < n ? i0 + B : n;
+    for (int64_t base = i0; base < i1; base += 64) {
         const int64_t i = base + t;
         const int32_t key = i < i1 ? keys[i] : -1;
-        ck[t] = key;
-        __syncthreads();
         int rank = 0;
         bool last = true;
-        if (key >= 0) {
-            for (int j = 0; j < t; ++j) rank += ck[j] == key ? 1 : 0;
-            for (int j = t + 1; j < 256; ++j) last = last && ck[j] != key;
-            perm[run[key] + rank] = (int32_t)i;
+        for (int j = 0; j < 64; ++j) {
+            const int32_t kj = __shfl(key, j);
+            if (kj == key) {
+                if (j < t) ++rank;
+                if (j > t) last = false;
+            }
         }
-        __syncthreads();
+        wave_lds_sync();
+        if (key >= 0) perm[run[key] + rank] = (int32_t)i;
+        wave_lds_sync();
         if (key >= 0 && last) run[key] += rank + 1;
+        wave_lds_sync();
+    }
+}
+
+// Parallel exclusive scan of int32 values (totals below 2^31): per-block
+// scans of 2048 values, a scan of the block sums, then the block offsets.
+constexpr int kScanBlock = 2048;
+
+__global__ __launch_bounds__(256) void scan_local_kernel(int32_t* v, int64_t n, int32_t* sums) {
+    __shared__ int32_t part[256];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + t * 8;
+    int32_t x[8];
+    int32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        x[j] = base + j < n ? v[base + j] : 0;
+        acc += x[j];
+    }
+    part[t] = acc;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t add = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += add;
         __syncthreads();
     }
+    int32_t run = t ? part[t - 1] : 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (base + j < n) v[base + j] = run;
+        run += x[j];
+    }
+    if (t == 255) sums[blockIdx.x] = part[255];
+}
+
+__global__ __launch_bounds__(256) void scan_add_kernel(int32_t* v, int64_t n, const int32_t* sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 8;
+    const int32_t add = sums[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (base + j < n) v[base + j] += add;
+}
+
+// In-place exclusive scan of n values; v[n] receives the total when
+// with_total is set.  sums needs ceil(n / 2048) + 1 entries.
+hipError_t launch_scan(int32_t* v, int64_t n, int32_t* sums, bool with_total, hipStream_t st) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb <= 1) {
+        hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1024), 0, st, v, n);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(scan_local_kernel, dim3((unsigned)nb), dim3(256), 0, st, v, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1024), 0, st, sums, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(256), 0, st, v, n,
+                       (const int32_t*)sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (with_total) {
+        // v[n] = sums[nb] (the grand total written by the sums scan)
+        e = hipMemcpyAsync(v + n, sums + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+    }
+    return e;
 }
 
 // offsets[r] = first position of key r, offsets[nk] = n.
@@ -134,19 +199,22 @@ __global__ void csort_offsets_kernel(const int32_t* start, int32_t nk, int32_t n
 }
 
 int csort_blocks(int64_t n) { return (int)((n + kSortBlock - 1) / kSortBlock); }
+int64_t csort_scratch(int64_t n, int32_t nk) {
+    const int64_t cells = (int64_t)nk * csort_blocks(n);
+    return cells + (cells + kScanBlock - 1) / kScanBlock + 2;
+}
 
 hipError_t launch_csort(const int32_t* keys, int64_t n, int32_t nk, int32_t* cnt, int32_t* perm,
                         int32_t* offsets, hipStream_t st) {
     const int nblk = csort_blocks(n);
+    const int64_t cells = (int64_t)nk * nblk;
     const size_t lds = (size_t)nk * sizeof(int32_t);
-    hipLaunchKernelGGL(csort_count_kernel, dim3(nblk), dim3(256), lds, st, keys, n, nk,
+    hipLaunchKernelGGL(csort_count_kernel, dim3(nblk), dim3(64), lds, st, keys, n, nk,
                        kSortBlock, nblk, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scan_1wg_kernel, dim3(1), dim3(1024), 0, st, cnt, (int64_t)nk * nblk);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(csort_scatter_kernel, dim3(nblk), dim3(256), lds, st, keys, n, nk,
+    if ((e = launch_scan(cnt, cells, cnt + cells, false, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(csort_scatter_kernel, dim3(nblk), dim3(64), lds, st, keys, n, nk,
                        kSortBlock, nblk, (const int32_t*)cnt, perm);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -160,27 +228,69 @@ hipError_t launch_csort(const int32_t* keys, int64_t n, int32_t nk, int32_t* cnt
 
 // ------------------------------------------------------------- list radii
 // psi_r = max over the points x owned by r of rho(x, r) (Sec. 4), in float64
-// with the fixed summation order; the maximum is taken on the bit patterns of
-// non-negative doubles, which order like the values.
-__global__ void psi_kernel(const float* X, int64_t ldx, int32_t d, int32_t metric, int64_t n,
-                           const int32_t* owner, const float* R, int64_t ldr,
-                           unsigned long long* psi_bits) {
+// with the fixed summation order.  A first pass takes the fp32 maximum per
+// list (16 lanes per point, any order); only points whose fp32 distance is
+// within the fp32 error of that maximum can hold the float64 maximum, and only
+// they are scored again in float64.  Maxima are taken on the bit patterns of
+// non-negative floats / doubles, which order like the values.
+__global__ __launch_bounds__(256) void psi32_kernel(const float* X, int64_t ldx, int32_t d,
+                                                    int32_t metric, int64_t n,
+                                                    const int32_t* owner, const float* R,
+                                                    int64_t ldr, float* dist32,
+                                                    uint32_t* max32) {
+    const int sub = threadIdx.x & 15;
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    float s = 0.f;
+    int32_t r = 0;
+    if (i < n) {
+        r = owner[i];
+        const float* xp = X + i * ldx;
+        const float* rp = R + (int64_t)r * ldr;
+        for (int f = sub; f < d; f += 16) {
+            const float t = xp[f] - rp[f];
+            s = metric == 0 ? __builtin_fmaf(t, t, s) : s + __builtin_fabsf(t);
+        }
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (i < n && sub == 0) {
+        const float v = metric == 0 ? __builtin_sqrtf(s) : s;
+        dist32[i] = v;
+        atomicMax(max32 + r, __float_as_uint(v));
+    }
+}
+
+__global__ void psi64_kernel(const float* X, int64_t ldx, int32_t d, int32_t metric, int64_t n,
+                             const int32_t* owner, const float* R, int64_t ldr,
+                             const float* dist32, const uint32_t* max32, double delta,
+                             unsigned long long* psi_bits) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t r = owner[i];
+    const double m32 = (double)__uint_as_float(max32[r]);
+    if ((double)dist32[i] < m32 * (1.0 - 2.0 * delta)) return;
     const double v = rho_fp64(X + i * ldx, R + (int64_t)r * ldr, d, metric);
     atomicMax(psi_bits + r, (unsigned long long)__double_as_longlong(v));
 }
 
 hipError_t launch_psi(const float* X, int64_t ldx, int32_t d, int32_t metric, int64_t n,
-                      const int32_t* owner, const float* R, int64_t ldr, double* psi,
-                      hipStream_t st) {
-    hipLaunchKernelGGL(psi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ldx, d,
-                       metric, n, owner, R, ldr, (unsigned long long*)psi);
+                      const int32_t* owner, const float* R, int64_t ldr, int32_t nr,
+                      float* dist32, uint32_t* max32, double* psi, hipStream_t st) {
+    hipError_t e;
+    if ((e = launch_fill_i32((int32_t*)max32, nr, 0, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i32((int32_t*)psi, 2 * (int64_t)nr, 0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(psi32_kernel, dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, st, X,
+                       ldx, d, metric, n, owner, R, ldr, dist32, max32);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const double delta = 2.0 * (d + 2) * 5.9604644775390625e-8;
+    hipLaunchKernelGGL(psi64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ldx,
+                       d, metric, n, owner, R, ldr, (const float*)dist32, (const uint32_t*)max32,
+                       delta, (unsigned long long*)psi);
     return hipGetLastError();
 }
 
 // --------------------------------------------------------------- stage 1
+constexpr int kDistReps = 64;  // representatives per workgroup (a multiple of 32)
 // DR[q][r] = rho(q, r) for every query and representative, fp32, direct
 // differences (the BF(q, R) call of Sec. 5.2 keeps every distance).  One
 // thread per query with the query in registers (d <= 128, KS 16-feature
@@ -195,6 +305,8 @@ __global__ __launch_bounds__(256) void dist_all_kernel(const float* Q, int64_t l
     __shared__ f4 rs[32 * F4];
     const int q = blockIdx.x * 256 + threadIdx.x;
     const bool qv = q < m;
+    const int rb0 = blockIdx.y * kDistReps;
+    const int rb1 = rb0 + kDistReps < nr ? rb0 + kDistReps : nr;
     f4 qr[F4];
     {
         const float* qp = Q + (int64_t)(qv ? q : 0) * ldq;
@@ -207,7 +319,7 @@ __global__ __launch_bounds__(256) void dist_all_kernel(const float* Q, int64_t l
             qr[j] = v;
         }
     }
-    for (int r0 = 0; r0 < nr; r0 += 32) {
+    for (int r0 = rb0; r0 < rb1; r0 += 32) {
         __syncthreads();
         for (int e = threadIdx.x; e < 32 * F4; e += 256) {
             const int rr = e / F4, cc = e - rr * F4;
@@ -260,7 +372,9 @@ __global__ __launch_bounds__(256) void dist_all_generic_kernel(const float* Q, i
     const int q = blockIdx.x * 256 + threadIdx.x;
     const bool qv = q < m;
     const float* qp = Q + (int64_t)(qv ? q : 0) * ldq;
-    for (int r0 = 0; r0 < nr; r0 += 32) {
+    const int rb0 = blockIdx.y * kDistReps;
+    const int rb1 = rb0 + kDistReps < nr ? rb0 + kDistReps : nr;
+    for (int r0 = rb0; r0 < rb1; r0 += 32) {
         float acc[32];
 #pragma unroll
         for (int j = 0; j < 32; ++j) acc[j] = 0.f;
@@ -322,7 +436,7 @@ static void launch_dist_ks(int ks, dim3 grid, hipStream_t st, const float* Q, in
 hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, const float* R,
                            int64_t ldr, int32_t nr, int32_t d, float* DR, int64_t ldd,
                            hipStream_t st) {
-    const dim3 grid((m + 255) / 256);
+    const dim3 grid((m + 255) / 256, (nr + kDistReps - 1) / kDistReps);
     // the register path needs 16-byte aligned representative rows
     const int ks = (ldr % 4 == 0 && ((uintptr_t)R & 15) == 0) ? (d + 15) / 16 : 0;
     if (metric == 0)
@@ -345,14 +459,12 @@ hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, c
 // Since R is a subset of X, gamma_c_up also bounds the distance of q's c-th
 // nearest database point; it seeds the stage-2 shortlists.
 // Outputs: lrank[q][r] = rank of r among the lists q keeps (-1: pruned),
-// keep_rq[r][q] (representative-major copy of the keep bits), nkept[q],
-// gcup[q].
+// nkept[q], gcup[q].
 __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd, int32_t m,
                                                     int32_t nr, int32_t k, int32_t c,
                                                     double delta, const double* psi,
                                                     const int32_t* list_off, int32_t* lrank,
-                                                    uint8_t* keep_rq, int32_t* nkept, float* gcup,
-                                                    int64_t* stats) {
+                                                    int32_t* nkept, float* gcup, int64_t* stats) {
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= m) return;
@@ -399,7 +511,6 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
         const uint64_t below = lane ? (bits & (~0ull >> (64 - lane))) : 0ull;
         if (r < nr) {
             lrank[(int64_t)q * nr + r] = kept ? running + __popcll(below) : -1;
-            keep_rq[(int64_t)r * m + q] = kept ? 1 : 0;
             if (kept) ncand += list_off[r + 1] - list_off[r];
         }
         running += __popcll(bits);
@@ -420,18 +531,44 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
 
 hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
                         double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
-                        uint8_t* keep_rq, int32_t* nkept, float* gcup, int64_t* stats,
-                        hipStream_t st) {
+                        int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st) {
     hipLaunchKernelGGL(prune_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, ldd, m, nr, k, c,
-                       delta, psi, list_off, lrank, keep_rq, nkept, gcup, stats);
+                       delta, psi, list_off, lrank, nkept, gcup, stats);
+    return hipGetLastError();
+}
+
+// keep_rq[r][q] = (lrank[q][r] >= 0), through 64 x 64 LDS tiles so that both
+// the reads and the writes are contiguous.
+__global__ __launch_bounds__(256) void keep_transpose_kernel(const int32_t* lrank, int32_t m,
+                                                             int32_t nr, uint8_t* keep_rq) {
+    __shared__ uint8_t tile[64][65];
+    const int q0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int qi = e >> 6, ri = e & 63;
+        const int q = q0 + qi, r = r0 + ri;
+        tile[qi][ri] = (q < m && r < nr && lrank[(int64_t)q * nr + r] >= 0) ? 1 : 0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int ri = e >> 6, qi = e & 63;
+        const int q = q0 + qi, r = r0 + ri;
+        if (q < m && r < nr) keep_rq[(int64_t)r * m + q] = tile[qi][ri];
+    }
+}
+
+hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(keep_transpose_kernel, dim3((m + 63) / 64, (nr + 63) / 64), dim3(256), 0, st,
+                       lrank, m, nr, keep_rq);
     return hipGetLastError();
 }
 
 // ------------------------------------------------ stage-2 work list (items)
 // Per representative (one wavefront each): how many queries kept it, and the
-// number of 256-query items it makes.
+// number of isize-query items it makes.
 __global__ __launch_bounds__(256) void rep_count_kernel(const uint8_t* keep_rq, int32_t m,
-                                                        int32_t nr, int32_t* cnt, int32_t* nitems) {
+                                                        int32_t nr, int32_t isize, int32_t* cnt,
+                                                        int32_t* nitems) {
     const int lane = threadIdx.x & 63;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= nr) return;
@@ -442,7 +579,7 @@ __global__ __launch_bounds__(256) void rep_count_kernel(const uint8_t* keep_rq, 
     for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
     if (lane == 0) {
         cnt[r] = c;
-        nitems[r] = (c + kTileQ - 1) / kTileQ;
+        nitems[r] = (c + isize - 1) / isize;
     }
 }
 
@@ -465,41 +602,16 @@ __global__ __launch_bounds__(256) void rep_fill_kernel(const uint8_t* keep_rq, i
     }
 }
 
-// In-place exclusive scan of v[0 .. n) by one workgroup; v[n] = the total.
-__global__ __launch_bounds__(1024) void scan_total_kernel(int32_t* v, int64_t n) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (n + 1023) / 1024;
-    const int64_t s = t * chunk;
-    const int64_t e = s + chunk < n ? s + chunk : n;
-    int64_t acc = 0;
-    for (int64_t i = s; i < e; ++i) acc += v[i];
-    part[t] = acc;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t add = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
-    }
-    int64_t run = t > 0 ? part[t - 1] : 0;
-    for (int64_t i = s; i < e; ++i) {
-        const int32_t x = v[i];
-        v[i] = (int32_t)run;
-        run += x;
-    }
-    if (t == 1023) v[n] = (int32_t)part[1023];
-}
-
 hipError_t launch_scan_total(int32_t* v, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1024), 0, st, v, n);
     return hipGetLastError();
 }
 
-hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_t* roff,
-                           int32_t* ioff, int32_t* qlist, hipStream_t st) {
+hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_t isize,
+                           int32_t* roff, int32_t* ioff, int32_t* qlist, hipStream_t st) {
     const dim3 grid((nr + 3) / 4);
-    hipLaunchKernelGGL(rep_count_kernel, grid, dim3(256), 0, st, keep_rq, m, nr, roff, ioff);
+    hipLaunchKernelGGL(rep_count_kernel, grid, dim3(256), 0, st, keep_rq, m, nr, isize, roff,
+                       ioff);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = launch_scan_total(roff, nr, st)) != hipSuccess) return e;
@@ -516,7 +628,8 @@ hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_
 //   mode 2 (direct l1, values rho):  gc (1 + delta)
 // each widened by a relative 4e-6; +inf when gc is.
 __global__ void tau_kernel(const float* gcup, const float* qn, const uint32_t* xmax_bits,
-                           int32_t m, int32_t d, int32_t mode, double delta, float* tau) {
+                           const uint32_t* flags_q, const uint32_t* flags_x, int32_t m, int32_t d,
+                           int32_t mode, double delta, float* tau) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= m) return;
     const double gc = (double)gcup[q];
@@ -526,7 +639,9 @@ __global__ void tau_kernel(const float* gcup, const float* qn, const uint32_t* x
         if (mode == 0) {
             const double n2 = (double)qn[q];
             const double sq = __builtin_sqrt(n2) + (double)__uint_as_float(*xmax_bits);
-            const double e = 4.0 * (d + 2) * 5.9604644775390625e-8 * sq * sq;
+            const double e = tile_exact(flags_q, flags_x, d)
+                                 ? 0.0
+                                 : 4.0 * (d + 2) * 5.9604644775390625e-8 * sq * sq;
             v = gc * gc * (1.0 + 4e-6) - n2 + 2.0 * e;
         } else if (mode == 1) {
             v = gc * gc * (1.0 + delta) * (1.0 + 4e-6);
@@ -538,10 +653,11 @@ __global__ void tau_kernel(const float* gcup, const float* qn, const uint32_t* x
     tau[q] = t;
 }
 
-hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits, int32_t m,
-                      int32_t d, int32_t mode, double delta, float* tau, hipStream_t st) {
-    hipLaunchKernelGGL(tau_kernel, dim3((m + 255) / 256), dim3(256), 0, st, gcup, qn, xmax_bits, m,
-                       d, mode, delta, tau);
+hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits,
+                      const uint32_t* flags_q, const uint32_t* flags_x, int32_t m, int32_t d,
+                      int32_t mode, double delta, float* tau, hipStream_t st) {
+    hipLaunchKernelGGL(tau_kernel, dim3((m + 255) / 256), dim3(256), 0, st, gcup, qn, xmax_bits,
+                       flags_q, flags_x, m, d, mode, delta, tau);
     return hipGetLastError();
 }
 

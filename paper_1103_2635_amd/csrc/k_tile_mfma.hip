@@ -20,13 +20,15 @@
 // [query][row], read back one query per lane), then every lane pushes its 32
 // values into a sorted register shortlist (TopC).
 //
-// Two launch forms share the row scan:
+// Three launch forms share the row scan:
 //   BF mode    -- grid (query blocks, database splits); a workgroup's 256
 //                 queries scan one split of the rows.
-//   item mode  -- exact RBC stage 2, a persistent grid pulling work items
-//                 (representative r, 256 of the queries that kept r) from a
-//                 queue; the queries scan the rows of L_r, their shortlists
-//                 start at a per-query threshold known from stage 1.
+//   item mode  -- RBC stage 2, persistent wavefronts pulling work items
+//                 (representative r, 64 of the queries that search L_r) from
+//                 a queue; the queries scan the rows of L_r, their shortlists
+//                 start at a per-query threshold known from stage 1 (exact
+//                 mode).
+//   all mode   -- every value written out (one-shot build).
 #include "rbc_device.h"
 
 #ifndef RBC_KS
@@ -174,12 +176,14 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma(Til
     }
 }
 
-// Exact RBC stage 2: persistent workgroups take (representative, query chunk)
-// items from the queue until it is empty.
+// RBC stage 2: persistent wavefronts, each taking (representative, 64-query
+// chunk) items from the queue until it is empty.  Wavefronts work
+// independently (no workgroup barrier); consecutive items usually belong to
+// the same representative, so co-resident wavefronts share its list rows in
+// the caches.
 template <int KS, int C>
 __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_items(TileArgs a) {
     __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
-    __shared__ int s_item;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -187,15 +191,13 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_ite
     const int total = *a.item_total;
 
     for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(a.item_queue, 1);
-        __syncthreads();
-        const int item = s_item;
+        int item = 0;
+        if (lane == 0) item = atomicAdd(a.item_queue, 1);
+        item = __shfl(item, 0);
         if (item >= total) break;
         const int r = item_rep(a, item);
-        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kTileQ + wave * kWave;
+        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kWave;
         const int q_end = a.roff[r + 1];
-        if (q_begin >= q_end) continue;  // uniform per wavefront; no barrier before the next item
 
         f4 qf[4][KS];
         int qrow[4];
@@ -210,11 +212,12 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_ite
         const bool valid = p < q_end;
         const int q = a.qlist[valid ? p : q_end - 1];
         TopC<C> top;
-        top.seed(a.tau[q]);
+        if (a.tau) top.seed(a.tau[q]); else top.init();
         scan_rows<KS, C>(qf, a.X, a.ldx, a.xn, a.n, a.d, a.list_off[r], a.list_off[r + 1], valid,
                          top, tbuf[wave], lane);
         if (valid) {
-            const int64_t pair = (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r];
+            const int64_t pair =
+                a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r] : (int64_t)q;
             top.store(a.pval + pair * C, a.pidx + pair * C);
         }
         if (a.stats && lane == 0) {
@@ -225,9 +228,81 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_ite
     }
 }
 
+// Every value of the tile written out (one-shot build): out[q * ldo + row] =
+// ||x||^2 - 2 q.x for the rows [blockIdx.y * rps, ...) of the split.
+template <int KS>
+__global__ __launch_bounds__(256, 2) void tile_l2_mfma_all(TileArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    const int slot0 = blockIdx.x * kTileQ + wave * kWave;
+    f4 qf[4][KS];
+    int qrow[4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+        const int slot = slot0 + 16 * qb + c16;
+        qrow[qb] = slot < a.m ? slot : a.m - 1;
+    }
+    load_qfrag<KS>(qf, a.Q, a.ldq, a.d, qrow, g);
+    const int r0 = (int)((int64_t)blockIdx.y * a.rps);
+    const int r1 = (int)(r0 + (int64_t)a.rps < a.n ? r0 + a.rps : a.n);
+    if (r0 >= r1) return;
+    f4 xa[2][KS];
+    load_xfrag<KS>(xa, a.X, a.ldx, a.n, a.d, r0, c16, g);
+    for (int base = r0; base < r1; base += kRowsMfma) {
+        f4 acc[2][4];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            f4 nv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = base + 16 * rb + 4 * g + i;
+                nv[i] = row < r1 ? a.xn[row] : RBC_INF;
+            }
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = nv;
+        }
+        f4 xb[2][KS];
+        const int next = base + kRowsMfma;
+        load_xfrag<KS>(xb, a.X, a.ldx, a.n, a.d, next < r1 ? next : base, c16, g);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int qb = 0; qb < 4; ++qb)
+                        acc[rb][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            xa[rb][s][j], qf[qb][s][j], acc[rb][qb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int row = base + 16 * rb + 4 * g;
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) {
+                const int slot = slot0 + 16 * qb + c16;
+                if (slot >= a.m) continue;
+                float* op = a.pval + (int64_t)slot * a.ldo + row;
+                if (row + 3 < r1) {
+                    *(f4*)op = acc[rb][qb];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (row + i < r1) op[i] = acc[rb][qb][i];
+                }
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) xa[rb][s] = xb[rb][s];
+    }
+}
+
 template <int KS, int C>
-static hipError_t launch_c(bool items, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (items)
+static hipError_t launch_c(int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
+    if (mode == kTileItems)
         hipLaunchKernelGGL((tile_l2_mfma_items<KS, C>), grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((tile_l2_mfma<KS, C>), grid, dim3(256), 0, st, a);
@@ -236,14 +311,18 @@ static hipError_t launch_c(bool items, dim3 grid, const TileArgs& a, hipStream_t
 
 // This file is compiled once per slab count RBC_KS (1..8); each object holds
 // that slab count's kernels for every shortlist length.
-hipError_t RBC_CAT(launch_tile_mfma_ks, RBC_KS)(int c, bool items, dim3 grid,
+hipError_t RBC_CAT(launch_tile_mfma_ks, RBC_KS)(int c, int mode, dim3 grid,
                                                 const TileArgs& a, hipStream_t st) {
+    if (mode == kTileAll) {
+        hipLaunchKernelGGL((tile_l2_mfma_all<RBC_KS>), grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     switch (c) {
-        case 4: return launch_c<RBC_KS, 4>(items, grid, a, st);
-        case 8: return launch_c<RBC_KS, 8>(items, grid, a, st);
-        case 16: return launch_c<RBC_KS, 16>(items, grid, a, st);
-        case 32: return launch_c<RBC_KS, 32>(items, grid, a, st);
-        case 64: return launch_c<RBC_KS, 64>(items, grid, a, st);
+        case 4: return launch_c<RBC_KS, 4>(mode, grid, a, st);
+        case 8: return launch_c<RBC_KS, 8>(mode, grid, a, st);
+        case 16: return launch_c<RBC_KS, 16>(mode, grid, a, st);
+        case 32: return launch_c<RBC_KS, 32>(mode, grid, a, st);
+        case 64: return launch_c<RBC_KS, 64>(mode, grid, a, st);
     }
     return hipErrorInvalidValue;
 }

@@ -107,11 +107,12 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         f4 qv[4 * KS];
         valu_load_q<KS>(qv, a.Q, a.ldq, a.d, q);
         TopC<C> top;
-        top.seed(a.tau[q]);
+        if (a.tau) top.seed(a.tau[q]); else top.init();
         valu_scan<METRIC, KS, C>(qv, a.X, a.ldx, a.d, a.list_off[r], a.list_off[r + 1], valid, top,
                                  xs);
         if (valid) {
-            const int64_t pair = (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r];
+            const int64_t pair =
+                a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r] : (int64_t)q;
             top.store(a.pval + pair * C, a.pidx + pair * C);
         }
         if (a.stats && threadIdx.x == 0) {
@@ -122,9 +123,53 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
     }
 }
 
+// Every value written out (one-shot build): out[q * ldo + row] = d^2 (l2) or
+// rho (l1), direct fp32, for the rows of split blockIdx.y.
+template <int METRIC, int KS>
+__global__ __launch_bounds__(256, 2) void tile_valu_all(TileArgs a) {
+    constexpr int F4 = 4 * KS;
+    __shared__ f4 xs[kRowsValu * F4];
+    const int myslot = blockIdx.x * kTileQ + threadIdx.x;
+    const bool qvalid = myslot < a.m;
+    f4 q[F4];
+    valu_load_q<KS>(q, a.Q, a.ldq, a.d, qvalid ? myslot : a.m - 1);
+    const int r0 = (int)((int64_t)blockIdx.y * a.rps);
+    const int r1 = (int)(r0 + (int64_t)a.rps < a.n ? r0 + a.rps : a.n);
+    for (int base = r0; base < r1; base += kRowsValu) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kRowsValu * F4; e += 256) {
+            const int rr = e / F4, cc = e - rr * F4;
+            const int row = base + rr;
+            f4 v = {0.f, 0.f, 0.f, 0.f};
+            if (row < r1 && 4 * cc < a.d) v = *(const f4*)(a.X + (int64_t)row * a.ldx + 4 * cc);
+            xs[e] = v;
+        }
+        __syncthreads();
+        if (!qvalid) continue;
+        const int nrow = r1 - base < kRowsValu ? r1 - base : kRowsValu;
+        float* op = a.pval + (int64_t)myslot * a.ldo + base;
+        for (int t = 0; t < nrow; ++t) {
+            f4 s = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < F4; ++j) {
+                const f4 df = q[j] - xs[t * F4 + j];
+                if (METRIC == 0) {
+                    s = df * df + s;
+                } else {
+                    s[0] += __builtin_fabsf(df[0]);
+                    s[1] += __builtin_fabsf(df[1]);
+                    s[2] += __builtin_fabsf(df[2]);
+                    s[3] += __builtin_fabsf(df[3]);
+                }
+            }
+            op[t] = (s[0] + s[1]) + (s[2] + s[3]);
+        }
+    }
+}
+
 template <int METRIC, int C>
-static hipError_t launch_c(bool items, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (items)
+static hipError_t launch_c(int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
+    if (mode == kTileItems)
         hipLaunchKernelGGL((tile_valu_items<METRIC, RBC_KS, C>), grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((tile_valu<METRIC, RBC_KS, C>), grid, dim3(256), 0, st, a);
@@ -132,21 +177,25 @@ static hipError_t launch_c(bool items, dim3 grid, const TileArgs& a, hipStream_t
 }
 
 template <int METRIC>
-static hipError_t launch_m(int c, bool items, dim3 grid, const TileArgs& a, hipStream_t st) {
+static hipError_t launch_m(int c, int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
+    if (mode == kTileAll) {
+        hipLaunchKernelGGL((tile_valu_all<METRIC, RBC_KS>), grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     switch (c) {
-        case 4: return launch_c<METRIC, 4>(items, grid, a, st);
-        case 8: return launch_c<METRIC, 8>(items, grid, a, st);
-        case 16: return launch_c<METRIC, 16>(items, grid, a, st);
-        case 32: return launch_c<METRIC, 32>(items, grid, a, st);
-        case 64: return launch_c<METRIC, 64>(items, grid, a, st);
+        case 4: return launch_c<METRIC, 4>(mode, grid, a, st);
+        case 8: return launch_c<METRIC, 8>(mode, grid, a, st);
+        case 16: return launch_c<METRIC, 16>(mode, grid, a, st);
+        case 32: return launch_c<METRIC, 32>(mode, grid, a, st);
+        case 64: return launch_c<METRIC, 64>(mode, grid, a, st);
     }
     return hipErrorInvalidValue;
 }
 
 // Compiled once per slab count RBC_KS (1..8).
-hipError_t RBC_CAT(launch_tile_valu_ks, RBC_KS)(int metric, int c, bool items, dim3 grid,
+hipError_t RBC_CAT(launch_tile_valu_ks, RBC_KS)(int metric, int c, int mode, dim3 grid,
                                                 const TileArgs& a, hipStream_t st) {
-    return metric == 0 ? launch_m<0>(c, items, grid, a, st) : launch_m<1>(c, items, grid, a, st);
+    return metric == 0 ? launch_m<0>(c, mode, grid, a, st) : launch_m<1>(c, mode, grid, a, st);
 }
 
 }  // namespace rbc

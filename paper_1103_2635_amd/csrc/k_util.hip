@@ -63,22 +63,62 @@ hipError_t launch_repack(const float* A, int64_t rows, int64_t lda, int32_t d, f
 // issues one atomic.  rowmap (optional) gives the source row of output row i.
 constexpr int kNormBlocks = 1024;
 
+// flags (optional, 3 words): [0] |= 2 (flags computed) and |= 1 if a value
+// is not an integer, [1] = max |value| as float bits, [2] |= 1 if a value is
+// negative.
 __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t rows, int64_t lda,
                                                         int32_t d, const int32_t* rowmap,
-                                                        float* out, uint32_t* maxbits) {
+                                                        float* out, uint32_t* maxbits,
+                                                        uint32_t* flags) {
     __shared__ float wmax[4];
+    __shared__ uint32_t wflag[4][3];
     const int sub = threadIdx.x & 15;
     float nmax = 0.f;
+    uint32_t nonint = 0, neg = 0;
+    float amax = 0.f;
     for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4; r < rows;
          r += ((int64_t)gridDim.x * blockDim.x) >> 4) {
         const int64_t src = rowmap ? rowmap[r] : r;
         const float* p = A + src * lda;
         float s = 0.f;
-        for (int f = sub; f < d; f += 16) s = __builtin_fmaf(p[f], p[f], s);
+        for (int f = sub; f < d; f += 16) {
+            const float v = p[f];
+            s = __builtin_fmaf(v, v, s);
+            if (flags) {
+                nonint |= (__builtin_rintf(v) != v) ? 1u : 0u;
+                neg |= v < 0.f ? 1u : 0u;
+                amax = fmaxf(amax, __builtin_fabsf(v));
+            }
+        }
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
         if (sub == 0) out[r] = s;
         nmax = fmaxf(nmax, __builtin_sqrtf(s));
+    }
+    if (flags) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            nonint |= __shfl_xor(nonint, off);
+            neg |= __shfl_xor(neg, off);
+            amax = fmaxf(amax, __shfl_xor(amax, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            wflag[threadIdx.x >> 6][0] = nonint;
+            wflag[threadIdx.x >> 6][1] = __float_as_uint(amax);
+            wflag[threadIdx.x >> 6][2] = neg;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t f0 = 0, f1 = 0, f2 = 0;
+            for (int w = 0; w < 4; ++w) {
+                f0 |= wflag[w][0];
+                f1 = f1 > wflag[w][1] ? f1 : wflag[w][1];
+                f2 |= wflag[w][2];
+            }
+            atomicOr(flags, f0 | 2u);
+            atomicMax(flags + 1, f1);
+            if (f2) atomicOr(flags + 2, f2);
+        }
     }
     if (maxbits) {
 #pragma unroll
@@ -92,12 +132,12 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t 
 
 hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d,
                             const int32_t* rowmap, float* out, uint32_t* maxbits,
-                            hipStream_t st) {
+                            hipStream_t st, uint32_t* flags) {
     if (rows <= 0) return hipSuccess;
     int64_t blocks = (rows * 16 + 255) / 256;
     if (blocks > kNormBlocks) blocks = kNormBlocks;
     hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, rows, lda,
-                       d, rowmap, out, maxbits);
+                       d, rowmap, out, maxbits, flags);
     return hipGetLastError();
 }
 

@@ -83,7 +83,7 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
 
 void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
     w->fb_list = cv.take<int32_t>(m);
-    w->counters = cv.take<int32_t>(4);
+    w->counters = cv.take<int32_t>(kCounters);
     if (p.path == kPathExact) return;
     if (p.repack_q) w->Qp = cv.take<float>(m * p.ldp);
     if (p.repack_x) w->Xp = cv.take<float>(n * p.ldp);
@@ -99,7 +99,7 @@ void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
 // the database rows, finalize, exhaustive fallback.  xn / xmax_bits may be
 // given (precomputed norms of X), id_map maps rows of X to reported ids.
 int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
-           int64_t ldx, const float* xn, const uint32_t* xmax_bits, const int64_t* id_map,
+           int64_t ldx, const float* xn, const uint32_t* xstat, const int64_t* id_map,
            int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st) {
     int32_t* fb_count = w.counters;
     int rc;
@@ -122,19 +122,19 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float*
         Xk = w.Xp;
         ldxk = p.ldp;
     }
-    if ((rc = hip_status(launch_fill_i32(w.counters, 4, 0, st), "clear counters"))) return rc;
-    const uint32_t* xmaxp = xmax_bits;
+    if ((rc = hip_status(launch_fill_i32(w.counters, kCounters, 0, st), "clear counters")))
+        return rc;
     if (p.path == kPathMfma) {
-        if ((rc = hip_status(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.qn, nullptr, st),
-                             "norms Q")))
+        if ((rc = hip_status(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.qn, nullptr, st,
+                                              (uint32_t*)w.counters + 5), "norms Q")))
             return rc;
         if (xn == nullptr) {
-            uint32_t* xm = (uint32_t*)(w.counters + 1);
-            if ((rc = hip_status(launch_row_norms(Xk, n, ldxk, p.d, nullptr, w.xn, xm, st),
+            uint32_t* xs = (uint32_t*)w.counters + 8;
+            if ((rc = hip_status(launch_row_norms(Xk, n, ldxk, p.d, nullptr, w.xn, xs, st, xs + 1),
                                  "norms X")))
                 return rc;
             xn = w.xn;
-            xmaxp = xm;
+            xstat = xs;
         }
     }
     TileArgs a;
@@ -156,19 +156,19 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float*
         KernelTimer kt("tile", st);
         const dim3 grid(p.nqblk, p.nsplit);
         rc = p.path == kPathMfma
-                 ? hip_status(launch_tile_mfma(p.ks, p.c, false, grid, a, st), "tile (mfma)")
-                 : hip_status(launch_tile_valu(p.metric, p.ks, p.c, false, grid, a, st),
+                 ? hip_status(launch_tile_mfma(p.ks, p.c, kTileBF, grid, a, st), "tile (mfma)")
+                 : hip_status(launch_tile_valu(p.metric, p.ks, p.c, kTileBF, grid, a, st),
                               "tile (valu)");
     }
     if (rc) return rc;
-    FinArgs f = fin_args(p, Qk, m, ldqk, Xk, ldxk, xmaxp, id_map, out_idx, out_dist, w, stats);
+    FinArgs f = fin_args(p, Qk, m, ldqk, Xk, ldxk, xstat, id_map, out_idx, out_dist, w, stats);
     f.nsplit = p.nsplit;
     if ((rc = run_finalize(p, f, st))) return rc;
     return run_fallback(p, Q, m, ldq, X, n, ldx, id_map, out_idx, out_dist, w, st);
 }
 
 FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, const float* Xk,
-                 int64_t ldxk, const uint32_t* xmax_bits, const int64_t* id_map,
+                 int64_t ldxk, const uint32_t* xstat, const int64_t* id_map,
                  int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats) {
     FinArgs f;
     std::memset(&f, 0, sizeof(f));
@@ -184,7 +184,9 @@ FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, cons
     f.pidx = w.pidx;
     f.k = p.k;
     f.qn = w.qn;
-    f.xmax_bits = xmax_bits;
+    f.xmax_bits = xstat;
+    f.flags_q = (const uint32_t*)w.counters + 5;
+    f.flags_x = xstat ? xstat + 1 : nullptr;
     f.id_map = id_map;
     f.out_idx = out_idx;
     f.out_dist = out_dist;

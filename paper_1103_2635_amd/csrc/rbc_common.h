@@ -20,6 +20,11 @@ constexpr int kRowsValu = 32;   // database rows per VALU tile
 constexpr int kMaxKS = 8;       // 16-feature slabs held in registers: d <= 128
 constexpr int kExactKCap = 1024;
 
+// tile launch forms
+constexpr int kTileBF = 0;     // partial shortlists per (split, query)
+constexpr int kTileItems = 1;  // persistent (representative, query chunk) items
+constexpr int kTileAll = 2;    // every value written to pval[q * ldo + row]
+
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // One tile launch.  BF mode: grid (query blocks of 256, database splits);
@@ -30,7 +35,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // covers queries qlist[roff[r] + (i - ioff[r]) * 256 ...] (at most 256, all
 // of which kept L_r); those queries scan the rows [list_off[r],
 // list_off[r + 1]) of X, starting from the shortlist threshold tau[q], and
-// leave their partial shortlist at pair qoff[q] + lrank[q * n_r + r].
+// leave their partial shortlist at pair qoff[q] + lrank[q * n_r + r] (exact
+// mode) or at pair q when lrank is null (one-shot: one list per query); tau
+// null means no seeded threshold.
 struct TileArgs {
     const float* Q;
     int64_t ldq;
@@ -52,8 +59,9 @@ struct TileArgs {
     const int32_t* qoff;
     const float* tau;
     int32_t n_r;
-    float* pval;           // partial shortlist values
+    float* pval;           // partial shortlist values (kTileAll: the value matrix)
     int32_t* pidx;         // partial shortlist rows (-1 = no row)
+    int64_t ldo;           // kTileAll: row stride of the value matrix
     int64_t* stats;        // optional device counters
 };
 
@@ -76,6 +84,8 @@ struct FinArgs {
     int32_t k;
     const float* qn;       // squared query norms (approx_mode 0)
     const uint32_t* xmax_bits;  // largest database row norm (float bits, approx_mode 0)
+    const uint32_t* flags_q;    // value flags of Q and X (see tile_exact), may be null
+    const uint32_t* flags_x;
     const int64_t* id_map; // row of X -> reported id (nullptr: identity)
     int64_t* out_idx;      // [rows of Q][k]
     float* out_dist;
@@ -97,6 +107,8 @@ struct ExactArgs {
     const int32_t* list;
     const int32_t* count;
     const int64_t* id_map;
+    const int32_t* qrep;      // optional: search only rows list_off[qrep[q]] .. list_off[qrep[q] + 1]
+    const int32_t* list_off;
     int64_t* out_idx;
     float* out_dist;
 };
@@ -109,18 +121,18 @@ hipError_t launch_repack(const float* A, int64_t rows, int64_t lda, int32_t d, f
                          int64_t ldo, hipStream_t st);
 hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d,
                             const int32_t* rowmap, float* out, uint32_t* maxbits,
+                            hipStream_t st, uint32_t* flags = nullptr);
+hipError_t launch_tile_mfma(int ks, int c, int mode, dim3 grid, const TileArgs& a,
                             hipStream_t st);
-hipError_t launch_tile_mfma(int ks, int c, bool items, dim3 grid, const TileArgs& a,
-                            hipStream_t st);
-hipError_t launch_tile_valu(int metric, int ks, int c, bool items, dim3 grid,
+hipError_t launch_tile_valu(int metric, int ks, int c, int mode, dim3 grid,
                             const TileArgs& a, hipStream_t st);
 
 #define RBC_CAT_(a, b) a##b
 #define RBC_CAT(a, b) RBC_CAT_(a, b)
 #define RBC_DECL_KS(n)                                                                     \
-    hipError_t launch_tile_mfma_ks##n(int c, bool items, dim3 grid, const TileArgs& a,     \
+    hipError_t launch_tile_mfma_ks##n(int c, int mode, dim3 grid, const TileArgs& a,       \
                                       hipStream_t st);                                     \
-    hipError_t launch_tile_valu_ks##n(int metric, int c, bool items, dim3 grid,            \
+    hipError_t launch_tile_valu_ks##n(int metric, int c, int mode, dim3 grid,              \
                                       const TileArgs& a, hipStream_t st);
 RBC_DECL_KS(1)
 RBC_DECL_KS(2)

@@ -26,6 +26,23 @@ static __device__ __noinline__ double rho_fp64(const float* a, const float* b, i
     return __builtin_sqrt(s);
 }
 
+// True when the matrix-core tile value ||x||^2 - 2 q.x is computed without
+// rounding: every input is an integer and every product and partial sum is
+// an integer of magnitude below 2^24 (exactly representable in fp32), in any
+// summation order.  With non-negative inputs all partial sums lie between
+// -d M^2 and d M^2 (M = the largest magnitude), otherwise within 3 d M^2.
+// fa / fb are value flags: [0] bit 1 = computed, bit 0 = non-integer seen,
+// [1] max |v| bits, [2] negative seen.
+__device__ __forceinline__ bool tile_exact(const uint32_t* fa, const uint32_t* fb, int d) {
+    if (!fa || !fb) return false;
+    if (fa[0] != 2u || fb[0] != 2u) return false;  // not computed, or a non-integer value
+    const double ma = (double)__uint_as_float(fa[1]);
+    const double mb = (double)__uint_as_float(fb[1]);
+    const double m = ma > mb ? ma : mb;
+    const bool neg = (fa[2] | fb[2]) != 0;
+    return neg ? 3.0 * d * m * m <= 16777216.0 : d * m * m <= 8388608.0;
+}
+
 // (distance, id) lexicographic order.
 __device__ __forceinline__ bool before(double va, int64_t ia, double vb, int64_t ib) {
     return va < vb || (va == vb && ia < ib);

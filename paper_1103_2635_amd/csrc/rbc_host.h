@@ -17,6 +17,9 @@ constexpr int kConcurrentBlocks = 512;  // 256 CUs x 2 resident tile workgroups
 constexpr int kMaxSplits = 64;          // one partial list per lane in finalize
 constexpr int kFallbackBlocks = 256;
 constexpr int kItemBlocks = 1024;       // persistent grid of the stage-2 item kernels
+constexpr int kCounters = 16;
+// A matrix "xstat" block: [0] largest row norm (float bits), [1..3] value
+// flags of tile_exact; 4 words, zeroed before the norms kernel fills it.
 
 int set_err(int status, const char* fmt, ...);
 const char* last_error();
@@ -57,7 +60,9 @@ struct BfPlan {
 
 struct BfWork {
     int32_t* fb_list = nullptr;
-    int32_t* counters = nullptr;  // [0] fallback count, [1] max row norm bits
+    // [0] fallback count, [2] work queue, [4..7] query stats (see xstat),
+    // [8..11] database stats: [8] max row norm bits, [9..11] value flags
+    int32_t* counters = nullptr;
     float* Qp = nullptr;
     float* Xp = nullptr;
     float* qn = nullptr;
@@ -83,11 +88,12 @@ private:
 int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int32_t metric,
                  int32_t k, const rbc_search_opts* opts, BfPlan* p);
 void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w);
+// xstat: precomputed stats of X (with xn), or null to compute them.
 int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
-           int64_t ldx, const float* xn, const uint32_t* xmax_bits, const int64_t* id_map,
+           int64_t ldx, const float* xn, const uint32_t* xstat, const int64_t* id_map,
            int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st);
 FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, const float* Xk,
-                 int64_t ldxk, const uint32_t* xmax_bits, const int64_t* id_map,
+                 int64_t ldxk, const uint32_t* xstat, const int64_t* id_map,
                  int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats);
 int run_finalize(const BfPlan& p, const FinArgs& f, hipStream_t st);
 int run_fallback(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X,

@@ -35,7 +35,7 @@ struct rbc_index {
     int32_t* list_off = nullptr; // n_r + 1 row offsets of the lists in Xp
     float* R = nullptr;          // representatives, n_r x ld
     double* psi = nullptr;       // list radii
-    uint32_t* norms_max = nullptr;  // [0] max row norm of Xp (float bits)
+    uint32_t* norms_max = nullptr;  // xstat of Xp: [0] max row norm bits, [1..3] value flags
     std::vector<int64_t> rep_host;
     std::vector<void*> allocs;
     size_t bytes = 0;
@@ -108,6 +108,33 @@ std::vector<int64_t> sample_reps(int64_t n, int64_t n_r, uint64_t seed) {
 
 int check(hipError_t e, const char* what) { return hip_status(e, what); }
 
+// Exhaustive float64 search of the listed queries, each restricted to the
+// list of its representative qrep[q] (one-shot).
+int run_fallback_lists(const BfPlan& p, const float* Q, int64_t m, int64_t ldq,
+                       const rbc_index* ix, const int32_t* qrep, int64_t* out_idx,
+                       float* out_dist, BfWork& w, hipStream_t st) {
+    ExactArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.Q = Q;
+    e.ldq = ldq;
+    e.X = ix->Xp;
+    e.ldx = ix->ld;
+    e.n = (int32_t)ix->rows;
+    e.d = ix->d;
+    e.metric = ix->metric;
+    e.k = p.k;
+    e.list = w.fb_list;
+    e.count = w.counters;
+    e.id_map = ix->ids;
+    e.qrep = qrep;
+    e.list_off = ix->list_off;
+    e.out_idx = out_idx;
+    e.out_dist = out_dist;
+    const int grid = p.path == kPathExact ? (int)std::min<int64_t>(m, 2048) : kFallbackBlocks;
+    KernelTimer kt("fallback", st);
+    return check(launch_exact(e, grid, st), "exact fallback");
+}
+
 int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     const int64_t n = ix->n, n_r = ix->n_r, ld = ix->ld;
     const int32_t d = ix->d;
@@ -126,7 +153,7 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     int64_t* own64 = nullptr;
     float* ownd = nullptr;
     if ((rc = s.take(&reps, n_r)) || (rc = s.take(&owner, n)) || (rc = s.take(&perm, n)) ||
-        (rc = s.take(&cnt, n_r * csort_blocks(n))) || (rc = s.take(&own64, n)) ||
+        (rc = s.take(&cnt, csort_scratch(n, (int32_t)n_r))) || (rc = s.take(&own64, n)) ||
         (rc = s.take(&ownd, n)))
         return rc;
     std::vector<int32_t> reps32(ix->rep_host.begin(), ix->rep_host.end());
@@ -157,11 +184,138 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     if ((rc = check(launch_gather_rows(X, ldx, d, perm, n, ix->Xp, ld, ix->ids, st), "gather Xp")))
         return rc;
     if ((rc = check(launch_fill_i32((int32_t*)ix->norms_max, 4, 0, st), "clear"))) return rc;
-    if ((rc = check(launch_row_norms(ix->Xp, n, ld, d, nullptr, ix->xn, ix->norms_max, st),
-                    "norms")))
+    if ((rc = check(launch_row_norms(ix->Xp, n, ld, d, nullptr, ix->xn, ix->norms_max, st,
+                                     ix->norms_max + 1), "norms")))
         return rc;
-    if ((rc = check(launch_fill_i32((int32_t*)ix->psi, 2 * n_r, 0, st), "clear psi"))) return rc;
-    if ((rc = check(launch_psi(X, ldx, d, ix->metric, n, owner, ix->R, ld, ix->psi, st), "psi")))
+    // ownd (the BF distances) and cnt are free again: reuse them as psi scratch
+    if ((rc = check(launch_psi(X, ldx, d, ix->metric, n, owner, ix->R, ld, (int32_t)n_r, ownd,
+                               (uint32_t*)cnt, ix->psi, st), "psi")))
+        return rc;
+    return check(hipStreamSynchronize(st), "build");
+}
+
+// One-shot build (Sec. 4, Sec. 5.1): BF(R, X) keeping every value, chunk by
+// chunk of representatives; each list is the s nearest points of its
+// representative in (float64 distance, id) order, psi_r the s-th distance.
+int build_oneshot(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
+    const int64_t n = ix->n, n_r = ix->n_r, s = ix->s, ld = ix->ld;
+    const int32_t d = ix->d;
+    if (s > kOsCap)
+        return set_err(RBC_EUNSUPPORTED, "one-shot list length s > %d", kOsCap);
+    if (n_r * s >= ((int64_t)1 << 31))
+        return set_err(RBC_EUNSUPPORTED, "n_r * s >= 2^31");
+    const int ks = (d + 15) / 16;
+    if (ks > kMaxKS) return set_err(RBC_EUNSUPPORTED, "one-shot build with d > %d", 16 * kMaxKS);
+    const bool mfma = ix->metric == RBC_L2 && d >= 12;
+    int rc;
+    ix->rows = n_r * s;
+    if ((rc = dev_alloc(ix, &ix->R, n_r * ld))) return rc;
+    if ((rc = dev_alloc(ix, &ix->psi, n_r))) return rc;
+    if ((rc = dev_alloc(ix, &ix->list_off, n_r + 1))) return rc;
+    if ((rc = dev_alloc(ix, &ix->Xp, ix->rows * ld))) return rc;
+    if ((rc = dev_alloc(ix, &ix->xn, ix->rows))) return rc;
+    if ((rc = dev_alloc(ix, &ix->ids, ix->rows))) return rc;
+    if ((rc = dev_alloc(ix, &ix->norms_max, 4))) return rc;
+
+    Scratch sc;
+    int32_t *reps = nullptr, *lists = nullptr, *ctr = nullptr;
+    float *rn2 = nullptr, *xnf = nullptr;
+    if ((rc = sc.take(&reps, n_r)) || (rc = sc.take(&lists, ix->rows)) || (rc = sc.take(&ctr, 8)) ||
+        (rc = sc.take(&rn2, n_r)) || (rc = sc.take(&xnf, n)))
+        return rc;
+    std::vector<int32_t> reps32(ix->rep_host.begin(), ix->rep_host.end());
+    if ((rc = check(hipMemcpyAsync(reps, reps32.data(), n_r * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st), "copy representatives")))
+        return rc;
+    if ((rc = check(launch_gather_rows(X, ldx, d, reps, n_r, ix->R, ld, nullptr, st), "gather R")))
+        return rc;
+    // the tile reads float4 rows: repack X when its layout does not allow it
+    const float* Xk = X;
+    int64_t ldxk = ldx;
+    if ((ldx % 4) || (d % 4)) {
+        float* xr = nullptr;
+        if ((rc = sc.take(&xr, n * ld))) return rc;
+        if ((rc = check(launch_repack(X, n, ldx, d, xr, ld, st), "repack X"))) return rc;
+        Xk = xr;
+        ldxk = ld;
+    }
+    if ((rc = check(launch_fill_i32(ctr, 8, 0, st), "clear"))) return rc;
+    uint32_t* xmax = (uint32_t*)ctr;  // xstat of X
+    if ((rc = check(launch_row_norms(Xk, n, ldxk, d, nullptr, xnf, xmax, st, xmax + 1), "norms X")))
+        return rc;
+    if ((rc = check(launch_row_norms(ix->R, n_r, ld, d, nullptr, rn2, nullptr, st), "norms R")))
+        return rc;
+    // value matrix of one chunk of representatives: at most 2 GiB
+    const int64_t ldv = (n + 3) / 4 * 4;
+    int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 31) / (ldv * 4));
+    chunk = std::min<int64_t>(chunk, n_r);
+    float* V = nullptr;
+    OneShotWork w;
+    if ((rc = sc.take(&V, chunk * ldv)) || (rc = sc.take(&w.hist, chunk * 4096)) ||
+        (rc = sc.take(&w.prefix, chunk)) || (rc = sc.take(&w.need, chunk)) ||
+        (rc = sc.take(&w.tval, chunk)) || (rc = sc.take(&w.bound, chunk)) ||
+        (rc = sc.take(&w.cnt, chunk)) || (rc = sc.take(&w.cand, chunk * kOsCap)))
+        return rc;
+    w.overflow = ctr + 4;
+    const double delta = 2.0 * (d + 2) * 5.9604644775390625e-8;
+    const int mode = mfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
+    for (int64_t c0 = 0; c0 < n_r; c0 += chunk) {
+        const int32_t rcnt = (int32_t)std::min<int64_t>(chunk, n_r - c0);
+        TileArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.Q = ix->R + c0 * ld;
+        a.ldq = ld;
+        a.m = rcnt;
+        a.X = Xk;
+        a.ldx = ldxk;
+        a.n = (int32_t)n;
+        a.d = d;
+        a.xn = xnf;
+        const int64_t nqb = (rcnt + kTileQ - 1) / kTileQ;
+        int64_t splits = std::max<int64_t>(1, (4 * kConcurrentBlocks) / nqb);
+        int64_t rps = (n + splits - 1) / splits;
+        rps = (rps + kRowsMfma - 1) / kRowsMfma * kRowsMfma;
+        a.rps = (int32_t)rps;
+        a.nsplit = (int32_t)((n + rps - 1) / rps);
+        a.pval = V;
+        a.ldo = ldv;
+        const dim3 grid((unsigned)nqb, (unsigned)a.nsplit);
+        {
+            KernelTimer kt("oneshot_tile", st);
+            rc = mfma ? check(launch_tile_mfma(ks, 4, kTileAll, grid, a, st), "one-shot tile")
+                      : check(launch_tile_valu(ix->metric, ks, 4, kTileAll, grid, a, st),
+                              "one-shot tile");
+        }
+        if (rc) return rc;
+        {
+            KernelTimer kt("oneshot_select", st);
+            if ((rc = check(launch_oneshot_select(V, ldv, (int32_t)n, rcnt, (int32_t)s, mode, delta,
+                                                  d, rn2 + c0, xmax, xmax + 1, w, st),
+                            "one-shot select")))
+                return rc;
+            if ((rc = check(launch_oneshot_sort(X, ldx, d, ix->metric, ix->R, ld, rcnt, (int32_t)s,
+                                                (int32_t)c0, w, lists, ix->psi, st),
+                            "one-shot sort")))
+                return rc;
+        }
+    }
+    int32_t overflow = 0;
+    if ((rc = check(hipMemcpyAsync(&overflow, w.overflow, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   st), "read overflow")) ||
+        (rc = check(hipStreamSynchronize(st), "one-shot lists")))
+        return rc;
+    if (overflow)
+        return set_err(RBC_EUNSUPPORTED,
+                       "%d representatives have more than %d points within the rounding margin "
+                       "of their s-th neighbour", overflow, kOsCap);
+    if ((rc = check(launch_gather_rows(X, ldx, d, lists, ix->rows, ix->Xp, ld, ix->ids, st),
+                    "gather lists")))
+        return rc;
+    if ((rc = check(launch_list_offsets(ix->list_off, (int32_t)n_r, (int32_t)s, st), "offsets")))
+        return rc;
+    if ((rc = check(launch_fill_i32((int32_t*)ix->norms_max, 4, 0, st), "clear"))) return rc;
+    if ((rc = check(launch_row_norms(ix->Xp, ix->rows, ld, d, nullptr, ix->xn, ix->norms_max, st,
+                                     ix->norms_max + 1), "norms")))
         return rc;
     return check(hipStreamSynchronize(st), "build");
 }
@@ -182,6 +336,122 @@ struct SearchWork {
 
 int64_t stage1_ld(int64_t nr) { return (nr + 3) / 4 * 4; }
 
+// One-shot search scratch: the nearest-representative BF (its own plan) and
+// the one-list-per-query stage 2.
+struct OneShotSearchWork {
+    BfPlan p1;
+    BfWork w1;            // BF(Q, R), k = 1
+    int64_t* near64 = nullptr;
+    float* neard = nullptr;
+    int32_t* nearest = nullptr;
+    int32_t* cnt = nullptr;
+    int32_t* qlist = nullptr;
+    int32_t* roff = nullptr;
+    int32_t* ioff = nullptr;
+};
+
+int carve_oneshot(const rbc_index* ix, const BfPlan& p, int64_t m, int64_t ldq, Carver& cv,
+                  SearchWork* w, OneShotSearchWork* o) {
+    int rc = make_bf_plan(m, ix->n_r, ix->d, ldq, ix->ld, ix->metric, 1, nullptr, &o->p1);
+    if (rc) return rc;
+    carve_bf(o->p1, m, ix->n_r, cv, &o->w1);
+    o->near64 = cv.take<int64_t>(m);
+    o->neard = cv.take<float>(m);
+    o->nearest = cv.take<int32_t>(m);
+    o->cnt = cv.take<int32_t>(csort_scratch(m, (int32_t)ix->n_r));
+    o->qlist = cv.take<int32_t>(m);
+    o->roff = cv.take<int32_t>(ix->n_r + 1);
+    o->ioff = cv.take<int32_t>(ix->n_r + 1);
+    if (p.path == kPathExact) {
+        carve_bf(p, m, ix->rows, cv, &w->bf);
+        return RBC_OK;
+    }
+    w->bf.fb_list = cv.take<int32_t>(m);
+    w->bf.counters = cv.take<int32_t>(kCounters);
+    if (p.repack_q) w->bf.Qp = cv.take<float>(m * p.ldp);
+    if (p.path == kPathMfma) w->bf.qn = cv.take<float>(m);
+    w->bf.pval = cv.take<float>(m * p.c);
+    w->bf.pidx = cv.take<int32_t>(m * p.c);
+    return RBC_OK;
+}
+
+// One-shot search, Sec. 5.1: r_q = the nearest representative (certified
+// BF(Q, R), ties to the lower position), then BF(q, L_{r_q}) for every query,
+// run as one grouped launch over (representative, query chunk) items.
+int search_oneshot(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m, int64_t ldq,
+                   int64_t* out_idx, float* out_dist, SearchWork& w, OneShotSearchWork& o,
+                   int64_t* stats, hipStream_t st) {
+    const int32_t nr = (int32_t)ix->n_r;
+    int rc;
+    {
+        KernelTimer kt("stage1", st);
+        if ((rc = run_bf(o.p1, Q, m, ldq, ix->R, nr, ix->ld, nullptr, nullptr, nullptr, o.near64,
+                         o.neard, o.w1, nullptr, st)))
+            return rc;
+    }
+    {
+        KernelTimer kt("worklist", st);
+        if ((rc = check(launch_narrow(o.near64, m, o.nearest, st), "nearest"))) return rc;
+        if ((rc = check(launch_csort(o.nearest, m, nr, o.cnt, o.qlist, o.roff, st), "group")))
+            return rc;
+        const int32_t isize = p.path == kPathMfma ? kWave : kTileQ;
+        if ((rc = check(launch_items_from_offsets(o.roff, nr, isize, o.ioff, st), "items")))
+            return rc;
+    }
+    if (p.path == kPathExact) {
+        // k beyond the register shortlist: exhaustive float64 inside each list
+        if ((rc = check(launch_iota_i32(w.bf.fb_list, (int32_t)m, st), "iota"))) return rc;
+        if ((rc = check(launch_set_count(w.bf.counters, (int32_t)m, st), "count"))) return rc;
+        return run_fallback_lists(p, Q, m, ldq, ix, o.nearest, out_idx, out_dist, w.bf, st);
+    }
+    const float* Qk = Q;
+    int64_t ldqk = ldq;
+    if (p.repack_q) {
+        if ((rc = check(launch_repack(Q, m, ldq, p.d, w.bf.Qp, p.ldp, st), "repack Q"))) return rc;
+        Qk = w.bf.Qp;
+        ldqk = p.ldp;
+    }
+    if ((rc = check(launch_fill_i32(w.bf.counters, kCounters, 0, st), "clear counters"))) return rc;
+    if (p.path == kPathMfma &&
+        (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st,
+                                     (uint32_t*)w.bf.counters + 5), "norms Q")))
+        return rc;
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = Qk;
+    a.ldq = ldqk;
+    a.m = (int32_t)m;
+    a.X = ix->Xp;
+    a.ldx = ix->ld;
+    a.n = (int32_t)ix->rows;
+    a.d = ix->d;
+    a.xn = ix->xn;
+    a.item_total = o.ioff + nr;
+    a.item_queue = w.bf.counters + 2;
+    a.ioff = o.ioff;
+    a.roff = o.roff;
+    a.qlist = o.qlist;
+    a.list_off = ix->list_off;
+    a.n_r = nr;
+    a.pval = w.bf.pval;
+    a.pidx = w.bf.pidx;
+    a.stats = stats;
+    {
+        KernelTimer kt("tile_items", st);
+        const dim3 grid(kItemBlocks);
+        rc = p.path == kPathMfma
+                 ? check(launch_tile_mfma(p.ks, p.c, kTileItems, grid, a, st), "stage 2 (mfma)")
+                 : check(launch_tile_valu(p.metric, p.ks, p.c, kTileItems, grid, a, st),
+                         "stage 2 (valu)");
+        if (rc) return rc;
+    }
+    FinArgs f = fin_args(p, Qk, m, ldqk, ix->Xp, ix->ld, ix->norms_max, ix->ids, out_idx,
+                         out_dist, w.bf, stats);
+    f.nsplit = 1;
+    if ((rc = run_finalize(p, f, st))) return rc;
+    return run_fallback_lists(p, Q, m, ldq, ix, o.nearest, out_idx, out_dist, w.bf, st);
+}
+
 void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, SearchWork* w) {
     if (p.path == kPathExact) {
         carve_bf(p, m, ix->rows, cv, &w->bf);
@@ -189,7 +459,7 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
     }
     const int64_t nr = ix->n_r;
     w->bf.fb_list = cv.take<int32_t>(m);
-    w->bf.counters = cv.take<int32_t>(4);
+    w->bf.counters = cv.take<int32_t>(kCounters);
     if (p.repack_q) w->bf.Qp = cv.take<float>(m * p.ldp);
     if (p.path == kPathMfma) w->bf.qn = cv.take<float>(m);
     w->bf.pval = cv.take<float>(m * nr * p.c);
@@ -208,8 +478,9 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
 
 int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
                 const rbc_search_opts* opts, BfPlan* p) {
-    if (ix->mode != RBC_EXACT) return set_err(RBC_EUNSUPPORTED, "one-shot search is not built yet");
-    if ((int64_t)m * ix->n_r >= ((int64_t)1 << 31))
+    if (ix->mode == RBC_ONESHOT && k > ix->s)
+        return set_err(RBC_EINVAL, "one-shot search needs k <= s (%lld)", (long long)ix->s);
+    if (ix->mode == RBC_EXACT && (int64_t)m * ix->n_r >= ((int64_t)1 << 31))
         return set_err(RBC_EUNSUPPORTED, "m * n_r >= 2^31: split the query batch");
     return make_bf_plan(m > 0 ? m : 1, ix->rows, ix->d, ldq, ix->ld, ix->metric, k, opts, p);
 }
@@ -238,7 +509,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
         Qk = w.bf.Qp;
         ldqk = p.ldp;
     }
-    if ((rc = check(launch_fill_i32(w.bf.counters, 4, 0, st), "clear counters"))) return rc;
+    if ((rc = check(launch_fill_i32(w.bf.counters, kCounters, 0, st), "clear counters"))) return rc;
     {
         KernelTimer kt("stage1", st);
         if ((rc = check(launch_dist_all(ix->metric, Q, ldq, (int32_t)m, ix->R, ix->ld, nr, ix->d,
@@ -248,8 +519,10 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     {
         KernelTimer kt("prune", st);
         if ((rc = check(launch_prune(w.DR, ldd, (int32_t)m, nr, k, p.c, delta, ix->psi,
-                                     ix->list_off, w.lrank, w.keep_rq, w.npairs, w.gcup, stats,
-                                     st), "prune")))
+                                     ix->list_off, w.lrank, w.npairs, w.gcup, stats, st),
+                        "prune")))
+            return rc;
+        if ((rc = check(launch_keep_transpose(w.lrank, (int32_t)m, nr, w.keep_rq, st), "keep")))
             return rc;
     }
     {
@@ -258,16 +531,18 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                                        hipMemcpyDeviceToDevice, st), "copy counts")))
             return rc;
         if ((rc = check(launch_scan_total(w.qoff, m, st), "pair offsets"))) return rc;
-        if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, w.roff, w.ioff, w.qlist, st),
-                        "work list")))
+        const int32_t isize = p.path == kPathMfma ? kWave : kTileQ;
+        if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, isize, w.roff, w.ioff, w.qlist,
+                                        st), "work list")))
             return rc;
         if (p.path == kPathMfma &&
-            (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st),
-                        "norms Q")))
+            (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st,
+                                         (uint32_t*)w.bf.counters + 5), "norms Q")))
             return rc;
         const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
-        if ((rc = check(launch_tau(w.gcup, w.bf.qn, ix->norms_max, (int32_t)m, ix->d, mode, delta,
-                                   w.tau, st), "thresholds")))
+        if ((rc = check(launch_tau(w.gcup, w.bf.qn, ix->norms_max,
+                                   (const uint32_t*)w.bf.counters + 5, ix->norms_max + 1,
+                                   (int32_t)m, ix->d, mode, delta, w.tau, st), "thresholds")))
             return rc;
     }
     TileArgs a;
@@ -297,8 +572,8 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
         KernelTimer kt("tile_items", st);
         const dim3 grid(kItemBlocks);
         rc = p.path == kPathMfma
-                 ? check(launch_tile_mfma(p.ks, p.c, true, grid, a, st), "stage 2 (mfma)")
-                 : check(launch_tile_valu(p.metric, p.ks, p.c, true, grid, a, st),
+                 ? check(launch_tile_mfma(p.ks, p.c, kTileItems, grid, a, st), "stage 2 (mfma)")
+                 : check(launch_tile_valu(p.metric, p.ks, p.c, kTileItems, grid, a, st),
                          "stage 2 (valu)");
         if (rc) return rc;
     }
@@ -332,10 +607,8 @@ int rbc_build(const float* X, int64_t n, int64_t ldx, int32_t d, const rbc_build
             return set_err(RBC_EINVAL, "n_r must be in [1, n] (got %lld)", (long long)prm->n_r);
         if (prm->n_r > kMaxReps)
             return set_err(RBC_EUNSUPPORTED, "n_r > %d", kMaxReps);
-        if (prm->mode == RBC_ONESHOT) {
-            if (prm->s < 1 || prm->s > n) return set_err(RBC_EINVAL, "s must be in [1, n]");
-            return set_err(RBC_EUNSUPPORTED, "one-shot build is not built yet");
-        }
+        if (prm->mode == RBC_ONESHOT && (prm->s < 1 || prm->s > n))
+            return set_err(RBC_EINVAL, "s must be in [1, n]");
         std::vector<int64_t> reps;
         if (prm->rep_idx) {
             reps.assign(prm->rep_idx, prm->rep_idx + prm->n_r);
@@ -361,7 +634,8 @@ int rbc_build(const float* X, int64_t n, int64_t ldx, int32_t d, const rbc_build
         ix->s = prm->s;
         ix->ld = ((int64_t)d + 3) / 4 * 4;
         ix->rep_host = std::move(reps);
-        rc = build_exact(ix, X, ldx, (hipStream_t)hip_stream);
+        rc = ix->mode == RBC_EXACT ? build_exact(ix, X, ldx, (hipStream_t)hip_stream)
+                                   : build_oneshot(ix, X, ldx, (hipStream_t)hip_stream);
         if (rc) {
             free_index(ix);
             return rc;
@@ -383,7 +657,12 @@ int rbc_search_workspace_size(const rbc_index* ix, int64_t m, int64_t ldq, int32
         if ((rc = search_plan(ix, m, ldq, k, opts, &p))) return rc;
         Carver cv(nullptr);
         SearchWork w;
-        carve_search(ix, p, m, cv, &w);
+        if (ix->mode == RBC_ONESHOT) {
+            OneShotSearchWork o;
+            if ((rc = carve_oneshot(ix, p, m > 0 ? m : 1, ldq, cv, &w, &o))) return rc;
+        } else {
+            carve_search(ix, p, m, cv, &w);
+        }
         *bytes = cv.size();
         return RBC_OK;
     } catch (...) {
@@ -404,12 +683,19 @@ int rbc_search(const rbc_index* ix, const float* Q, int64_t m, int64_t ldq, int3
         if ((rc = search_plan(ix, m, ldq, k, opts, &p))) return rc;
         Carver cv((char*)workspace);
         SearchWork w;
-        carve_search(ix, p, m, cv, &w);
+        OneShotSearchWork o;
+        if (ix->mode == RBC_ONESHOT) {
+            if ((rc = carve_oneshot(ix, p, m, ldq, cv, &w, &o))) return rc;
+        } else {
+            carve_search(ix, p, m, cv, &w);
+        }
         if (!workspace || ws_bytes < cv.size())
             return set_err(RBC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu needed",
                            ws_bytes, cv.size());
         hipStream_t st = (hipStream_t)hip_stream;
         int64_t* stats = opts ? opts->dev_stats : nullptr;
+        if (ix->mode == RBC_ONESHOT)
+            return search_oneshot(ix, p, Q, m, ldq, out_idx, out_dist, w, o, stats, st);
         if (p.path == kPathExact)
             return run_bf(p, Q, m, ldq, ix->Xp, ix->rows, ix->ld, nullptr, nullptr, ix->ids,
                           out_idx, out_dist, w.bf, stats, st);

@@ -7,32 +7,67 @@ namespace rbc {
 
 constexpr int kSortBlock = 4096;   // items per block of the stable counting sort
 constexpr int kMaxReps = 16384;    // LDS histogram of the counting sort
+constexpr int kOsCap = 8192;       // one-shot build: candidates per representative (LDS sort)
+
+// Scratch of the one-shot list selection for a chunk of representatives.
+struct OneShotWork {
+    uint32_t* hist = nullptr;    // reps x 4096
+    uint32_t* prefix = nullptr;  // reps
+    int32_t* need = nullptr;     // reps
+    float* tval = nullptr;       // reps
+    float* bound = nullptr;      // reps
+    int32_t* cnt = nullptr;      // reps
+    int32_t* cand = nullptr;     // reps x kOsCap
+    int32_t* overflow = nullptr; // 1
+};
 
 int csort_blocks(int64_t n);
+// int32 scratch entries launch_csort needs for n items and nk keys
+int64_t csort_scratch(int64_t n, int32_t nk);
+// in-place exclusive scan; sums needs ceil(n / 2048) + 1 entries; v[n] = total if with_total
+hipError_t launch_scan(int32_t* v, int64_t n, int32_t* sums, bool with_total, hipStream_t st);
 hipError_t launch_gather_rows(const float* A, int64_t lda, int32_t d, const int32_t* rows,
                               int64_t nrows, float* out, int64_t ldo, int64_t* ids_out,
                               hipStream_t st);
 hipError_t launch_narrow(const int64_t* in, int64_t n, int32_t* out, hipStream_t st);
 // keys -> perm (items ordered by (key, item)), offsets[nk + 1] (optional);
-// cnt needs nk * csort_blocks(n) int32.
+// cnt needs csort_scratch(n, nk) int32.
 hipError_t launch_csort(const int32_t* keys, int64_t n, int32_t nk, int32_t* cnt, int32_t* perm,
                         int32_t* offsets, hipStream_t st);
+// dist32: n floats, max32: nr uint32 of scratch
 hipError_t launch_psi(const float* X, int64_t ldx, int32_t d, int32_t metric, int64_t n,
-                      const int32_t* owner, const float* R, int64_t ldr, double* psi,
-                      hipStream_t st);
+                      const int32_t* owner, const float* R, int64_t ldr, int32_t nr,
+                      float* dist32, uint32_t* max32, double* psi, hipStream_t st);
 hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, const float* R,
                            int64_t ldr, int32_t nr, int32_t d, float* DR, int64_t ldd,
                            hipStream_t st);
 hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
                         double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
-                        uint8_t* keep_rq, int32_t* nkept, float* gcup, int64_t* stats,
-                        hipStream_t st);
+                        int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st);
+hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
+                                 hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.
-hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_t* roff,
-                           int32_t* ioff, int32_t* qlist, hipStream_t st);
+hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_t isize,
+                           int32_t* roff, int32_t* ioff, int32_t* qlist, hipStream_t st);
 // exclusive scan of v[0 .. n), total to v[n]
 hipError_t launch_scan_total(int32_t* v, int64_t n, hipStream_t st);
-hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits, int32_t m,
-                      int32_t d, int32_t mode, double delta, float* tau, hipStream_t st);
+hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits,
+                      const uint32_t* flags_q, const uint32_t* flags_x, int32_t m, int32_t d,
+                      int32_t mode, double delta, float* tau, hipStream_t st);
+
+// One-shot build, per chunk of `reps` representatives whose values (tile
+// value space given by mode) are V[rep][0 .. n): candidate rows of each list.
+hipError_t launch_oneshot_select(const float* V, int64_t ldv, int32_t n, int32_t reps, int32_t s,
+                                 int32_t mode, double delta, int32_t d, const float* rnorm2,
+                                 const uint32_t* xmax_bits, const uint32_t* flags, OneShotWork& w,
+                                 hipStream_t st);
+// float64 re-score and sort of the candidates: lists[rep0 + rep][0 .. s), psi.
+hipError_t launch_oneshot_sort(const float* X, int64_t ldx, int32_t d, int32_t metric,
+                               const float* R, int64_t ldr, int32_t reps, int32_t s, int32_t rep0,
+                               OneShotWork& w, int32_t* lists, double* psi, hipStream_t st);
+// ioff[r] = items of representative r from query offsets roff, scanned; ioff[nr] = total.
+hipError_t launch_items_from_offsets(const int32_t* roff, int32_t nr, int32_t isize,
+                                     int32_t* ioff, hipStream_t st);
+hipError_t launch_list_offsets(int32_t* off, int32_t nr, int32_t s, hipStream_t st);
 
 }  // namespace rbc
