@@ -48,8 +48,12 @@ extern "C" {
 /* Metric rho (Sec. 4; the l1 form is the one written out in Sec. 6). */
 typedef enum { RBC_L2 = 0, RBC_L1 = 1 } rbc_metric;
 
-/* Arithmetic of the distance contraction.  RBC_FP32 is the only precision
- * of this version; the others return RBC_EUNSUPPORTED. */
+/* Arithmetic of the distance contraction (matrix cores, fp32 accumulate).
+ * RBC_BF16 and RBC_FP8_E4M3 (OCP e4m3, per-row power-of-two scale) apply to
+ * bf_search with RBC_L2 and d <= 128: candidates are ranked on quantised
+ * rows, re-scored in fp32 from the original rows, certified with the
+ * quantisation error added to the bound, near-ties re-ranked in float64;
+ * results are as exact as with RBC_FP32. */
 typedef enum { RBC_FP32 = 0, RBC_BF16 = 1, RBC_FP8_E4M3 = 2 } rbc_precision;
 
 /* Ownership rule of the index (Sec. 4): RBC_EXACT -- each point is owned by
@@ -88,6 +92,9 @@ typedef struct rbc_search_opts {
     int32_t splits;     /* database splits per query block (0 = automatic) */
     int32_t flags;      /* reserved, must be 0 */
     int64_t* dev_stats; /* optional DEVICE array of RBC_STATS_LEN int64 counters */
+    float* dev_approx_dist; /* optional DEVICE m x k floats: the distance each result had in
+                               the ranking tile, before re-scoring (not written for queries
+                               that take the float64 fallback) */
 } rbc_search_opts;
 
 /* Index construction parameters. */
@@ -114,7 +121,7 @@ typedef struct rbc_index rbc_index; /* opaque; owns its device memory */
  *   call queues on `stream`.  Q and X must be 16-byte aligned.
  * Errors: RBC_EINVAL for d < 1, n < 1, k < 1, k > n, ldq < d, ldx < d,
  * m < 0, NULL pointers with m > 0; RBC_EUNSUPPORTED for d > RBC_MAX_D,
- * k > RBC_MAX_K, n >= 2^31, or a precision other than RBC_FP32;
+ * k > RBC_MAX_K, n >= 2^31, or a low precision with RBC_L1 or d > 128;
  * RBC_EWORKSPACE when the workspace is too small.
  */
 int bf_search_workspace_size(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx,

@@ -34,7 +34,7 @@ _SZ = ctypes.c_size_t
 
 class SearchOpts(ctypes.Structure):
     _fields_ = [("precision", _I32), ("shortlist", _I32), ("splits", _I32), ("flags", _I32),
-                ("dev_stats", _P)]
+                ("dev_stats", _P), ("dev_approx_dist", _P)]
 
 
 class BuildParams(ctypes.Structure):
@@ -98,7 +98,7 @@ def _mat(t, name):
     return t
 
 
-def _opts(precision="fp32", shortlist=0, splits=0, stats=None):
+def _opts(precision="fp32", shortlist=0, splits=0, stats=None, approx_dist=None):
     o = SearchOpts()
     o.precision = _PRECS[precision]
     o.shortlist = int(shortlist)
@@ -108,6 +108,10 @@ def _opts(precision="fp32", shortlist=0, splits=0, stats=None):
         if stats.dtype != torch.int64 or not stats.is_cuda or stats.numel() < STATS_LEN:
             raise ValueError("stats must be a GPU int64 tensor of %d counters" % STATS_LEN)
         o.dev_stats = stats.data_ptr()
+    if approx_dist is not None:
+        if approx_dist.dtype != torch.float32 or not approx_dist.is_cuda:
+            raise ValueError("approx_dist must be a GPU float32 tensor of m x k")
+        o.dev_approx_dist = approx_dist.data_ptr()
     return o
 
 
@@ -128,8 +132,9 @@ def bf_search(Q, X, k, metric="l2", out=None, workspace=None, **kw):
     """BF(Q, X): the k nearest rows of X for every row of Q.
 
     Returns (idx int64 [m, k], dist float32 [m, k]) on Q's device, each row
-    sorted by (distance, id).  Keyword options: precision, shortlist, splits,
-    stats (see new_stats)."""
+    sorted by (distance, id).  Keyword options: precision ("fp32", "bf16",
+    "fp8"), shortlist, splits, stats (see new_stats), approx_dist (a GPU
+    float32 m x k tensor that receives the pre-re-score distances)."""
     _mat(Q, "Q")
     _mat(X, "X")
     m, d = Q.shape

@@ -24,7 +24,8 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 PER_KS = ["k_tile_mfma.hip", "k_tile_valu.hip"]
-SINGLE = ["k_util.hip", "k_finalize.hip", "k_rbc.hip", "k_oneshot.hip", "rbc_dispatch.cpp", "rbc_api.cpp",
+PER_KB = ["k_tile_lowp.hip"]
+SINGLE = ["k_util.hip", "k_finalize.hip", "k_rbc.hip", "k_oneshot.hip", "k_quant.hip", "rbc_dispatch.cpp", "rbc_api.cpp",
           "rbc_index.cpp", "rbc_timer.cpp"]
 
 
@@ -34,6 +35,10 @@ def _units():
         for ks in range(1, 9):
             obj = os.path.join(BUILD, "%s.ks%d.o" % (os.path.splitext(src)[0], ks))
             units.append((src, obj, ["-DRBC_KS=%d" % ks]))
+    for src in PER_KB:
+        for kb in range(1, 5):
+            obj = os.path.join(BUILD, "%s.kb%d.o" % (os.path.splitext(src)[0], kb))
+            units.append((src, obj, ["-DRBC_KB=%d" % kb]))
     for src in SINGLE:
         if os.path.exists(os.path.join(CSRC, src)):
             units.append((src, os.path.join(BUILD, os.path.splitext(src)[0] + ".o"), []))

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         const uint64_t kth = __ballot(valid && rank == a.k - 1);
         const double t_k = __shfl(rho, (int)__builtin_ctzll(kth));
         double lo;
-        if (a.approx_mode == 0) {
+        if (a.approx_mode == 0 || a.approx_mode == 2) {
             const double qn = a.qn[slot];
             const double xmax = (double)__uint_as_float(*a.xmax_bits);
             const double sq = __builtin_sqrt(qn) + xmax;
@@ -157,6 +157,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
                 tile_exact(a.flags_q, a.flags_x, a.d) ? 0.0 : 4.0 * (a.d + 2) * u * sq * sq;
             const double lo2 = (double)a_c + qn - e;
             lo = lo2 > 0.0 ? __builtin_sqrt(lo2) : 0.0;
+            if (a.approx_mode == 2)  // distances of the quantised rows: triangle inequality
+                lo -= (double)a.qerr[slot] + (double)__uint_as_float(*a.xerr_max_bits);
         } else if (a.metric == 0) {
             lo = __builtin_sqrt((double)a_c) * (1.0 - delta);
         } else {
@@ -173,6 +175,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     } else if (valid && rank < a.k) {
         a.out_idx[(int64_t)qrow * a.k + rank] = myid;
         a.out_dist[(int64_t)qrow * a.k + rank] = (float)rho;
+        if (a.out_approx) {
+            // the entry's distance in the ranking tile, before re-scoring
+            double ap;
+            if (a.approx_mode == 1)
+                ap = a.metric == 0 ? __builtin_sqrt((double)mv) : (double)mv;
+            else
+                ap = __builtin_sqrt(fmax((double)mv + (double)a.qn[slot], 0.0));
+            a.out_approx[(int64_t)qrow * a.k + rank] = (float)ap;
+        }
     }
     if (a.stats && lane == 0) {
         if (!ok) atomicAdd((unsigned long long*)&a.stats[0], 1ull);

@@ -46,8 +46,10 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
                  int32_t k, const rbc_search_opts* opts, BfPlan* p) {
     std::memset(p, 0, sizeof(*p));
     const int prec = opts ? opts->precision : RBC_FP32;
-    if (prec != RBC_FP32)
-        return set_err(RBC_EUNSUPPORTED, "precision %d is not implemented (only RBC_FP32)", prec);
+    if (prec != RBC_FP32 && prec != RBC_BF16 && prec != RBC_FP8_E4M3)
+        return set_err(RBC_EINVAL, "unknown precision %d", prec);
+    if (prec != RBC_FP32 && (metric != RBC_L2 || d > 128))
+        return set_err(RBC_EUNSUPPORTED, "low precision needs the L2 metric and d <= 128");
     if (opts && opts->flags != 0) return set_err(RBC_EINVAL, "opts->flags must be 0");
     p->metric = metric;
     p->k = k;
@@ -55,13 +57,20 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
     p->ldp = ((int64_t)d + 3) / 4 * 4;
     p->repack_q = (d % 4) != 0 || (ldq % 4) != 0;
     p->repack_x = (d % 4) != 0 || (ldx % 4) != 0;
-    p->c = shortlist_len(k, opts ? opts->shortlist : 0);
+    p->prec = prec;
+    // low precision ranks on quantised rows: a longer default shortlist (32)
+    p->c = shortlist_len(k, opts && opts->shortlist ? opts->shortlist : (prec != RBC_FP32 ? 32 : 0));
     p->ks = (d + 15) / 16;
     if (p->c == 0 || p->ks > kMaxKS) {
         p->path = kPathExact;
         p->c = 0;
         p->ks = 0;
         p->repack_q = p->repack_x = false;
+    } else if (prec != RBC_FP32) {
+        p->path = kPathLowp;
+        p->repack_q = p->repack_x = false;  // the quantiser reads any stride
+        p->kb = prec == RBC_BF16 ? (d + 31) / 32 : 1;
+        p->dq = prec == RBC_BF16 ? 32 * p->kb : 128;
     } else if (metric == RBC_L2 && d >= 12) {
         p->path = kPathMfma;
     } else {
@@ -87,12 +96,77 @@ void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
     if (p.path == kPathExact) return;
     if (p.repack_q) w->Qp = cv.take<float>(m * p.ldp);
     if (p.repack_x) w->Xp = cv.take<float>(n * p.ldp);
-    if (p.path == kPathMfma) {
+    if (p.path == kPathMfma || p.path == kPathLowp) {
         w->qn = cv.take<float>(m);
         w->xn = cv.take<float>(n);
     }
+    if (p.path == kPathLowp) {
+        const int64_t esz = p.prec == RBC_BF16 ? 2 : 1;
+        w->Qq = cv.take<uint8_t>(m * p.dq * esz);
+        w->Xq = cv.take<uint8_t>(n * p.dq * esz);
+        w->qerr = cv.take<float>(m);
+        if (p.prec == RBC_FP8_E4M3) {
+            w->qscale = cv.take<uint8_t>(m);
+            w->xscale = cv.take<uint8_t>(n);
+        }
+    }
     w->pval = cv.take<float>((int64_t)p.nsplit * m * p.c);
     w->pidx = cv.take<int32_t>((int64_t)p.nsplit * m * p.c);
+}
+
+// BF(Q, X) with the contraction on quantised rows: quantise Q (times -2) and
+// X, run the bf16 / fp8 tile, finalize (re-score from the fp32 rows; the
+// certificate adds the quantisation errors), fallback.
+int run_bf_lowp(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
+                int64_t ldx, const int64_t* id_map, int64_t* out_idx, float* out_dist, BfWork& w,
+                int64_t* stats, hipStream_t st, float* out_approx) {
+    int rc;
+    const int fmt = p.prec == RBC_BF16 ? 0 : 1;
+    if ((rc = hip_status(launch_fill_i32(w.counters, kCounters, 0, st), "clear counters")))
+        return rc;
+    uint32_t* ctr = (uint32_t*)w.counters;
+    {
+        KernelTimer kt("quantize", st);
+        if ((rc = hip_status(launch_quantize(fmt, Q, m, ldq, p.d, -2.0f, w.Qq, p.dq, p.dq, w.qn,
+                                             w.qerr, w.qscale, ctr + 14, st), "quantize Q")))
+            return rc;
+        if ((rc = hip_status(launch_quantize(fmt, X, n, ldx, p.d, 1.0f, w.Xq, p.dq, p.dq, w.xn,
+                                             nullptr, w.xscale, ctr + 12, st), "quantize X")))
+            return rc;
+    }
+    // w.qn / w.xn now hold ||q~||^2 and ||x~||^2 of the quantised rows
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = (const float*)w.Qq;
+    a.ldq = p.dq;
+    a.m = (int32_t)m;
+    a.X = (const float*)w.Xq;
+    a.ldx = p.dq;
+    a.n = (int32_t)n;
+    a.d = p.d;
+    a.xn = w.xn;
+    a.rps = p.rps;
+    a.nsplit = p.nsplit;
+    a.qscale = w.qscale;
+    a.xscale = w.xscale;
+    a.pval = w.pval;
+    a.pidx = w.pidx;
+    a.stats = stats;
+    {
+        KernelTimer kt("tile", st);
+        const dim3 grid(p.nqblk, p.nsplit);
+        if ((rc = hip_status(launch_tile_lowp(fmt, p.kb, p.c, grid, a, st), "tile (low precision)")))
+            return rc;
+    }
+    FinArgs f = fin_args(p, Q, m, ldq, X, ldx, ctr + 12, id_map, out_idx, out_dist, w, stats,
+                         out_approx);
+    f.nsplit = p.nsplit;
+    f.qerr = w.qerr;
+    f.xerr_max_bits = ctr + 13;
+    f.flags_q = nullptr;
+    f.flags_x = nullptr;
+    if ((rc = run_finalize(p, f, st))) return rc;
+    return run_fallback(p, Q, m, ldq, X, n, ldx, id_map, out_idx, out_dist, w, st);
 }
 
 // The launch sequence of BF(Q, X) (bf_search and the RBC build): tile over
@@ -100,9 +174,13 @@ void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
 // given (precomputed norms of X), id_map maps rows of X to reported ids.
 int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
            int64_t ldx, const float* xn, const uint32_t* xstat, const int64_t* id_map,
-           int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st) {
+           int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st,
+           float* out_approx) {
     int32_t* fb_count = w.counters;
     int rc;
+    if (p.path == kPathLowp)
+        return run_bf_lowp(p, Q, m, ldq, X, n, ldx, id_map, out_idx, out_dist, w, stats, st,
+                           out_approx);
     if (p.path == kPathExact) {
         if ((rc = hip_status(launch_iota_i32(w.fb_list, (int32_t)m, st), "iota"))) return rc;
         if ((rc = hip_status(launch_set_count(fb_count, (int32_t)m, st), "set_count"))) return rc;
@@ -161,7 +239,8 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float*
                               "tile (valu)");
     }
     if (rc) return rc;
-    FinArgs f = fin_args(p, Qk, m, ldqk, Xk, ldxk, xstat, id_map, out_idx, out_dist, w, stats);
+    FinArgs f = fin_args(p, Qk, m, ldqk, Xk, ldxk, xstat, id_map, out_idx, out_dist, w, stats,
+                         out_approx);
     f.nsplit = p.nsplit;
     if ((rc = run_finalize(p, f, st))) return rc;
     return run_fallback(p, Q, m, ldq, X, n, ldx, id_map, out_idx, out_dist, w, st);
@@ -169,7 +248,8 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float*
 
 FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, const float* Xk,
                  int64_t ldxk, const uint32_t* xstat, const int64_t* id_map,
-                 int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats) {
+                 int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats,
+                 float* out_approx) {
     FinArgs f;
     std::memset(&f, 0, sizeof(f));
     f.Q = Qk;
@@ -179,7 +259,8 @@ FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, cons
     f.ldx = ldxk;
     f.d = p.d;
     f.metric = p.metric;
-    f.approx_mode = p.path == kPathMfma ? 0 : 1;
+    f.approx_mode = p.path == kPathMfma ? 0 : (p.path == kPathLowp ? 2 : 1);
+    f.out_approx = out_approx;
     f.pval = w.pval;
     f.pidx = w.pidx;
     f.k = p.k;
@@ -290,7 +371,8 @@ int bf_search(const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
             return set_err(RBC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu needed",
                            ws_bytes, cv.size());
         return run_bf(p, Q, m, ldq, X, n, ldx, nullptr, nullptr, nullptr, out_idx, out_dist, w,
-                      opts ? opts->dev_stats : nullptr, (hipStream_t)hip_stream);
+                      opts ? opts->dev_stats : nullptr, (hipStream_t)hip_stream,
+                      opts ? opts->dev_approx_dist : nullptr);
     } catch (...) {
         return set_err(RBC_EHIP, "unexpected exception");
     }

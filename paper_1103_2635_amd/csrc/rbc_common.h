@@ -59,6 +59,8 @@ struct TileArgs {
     const int32_t* qoff;
     const float* tau;
     int32_t n_r;
+    const uint8_t* qscale;  // fp8 tiles: per-row E8M0 scale bytes of Q and X
+    const uint8_t* xscale;
     float* pval;           // partial shortlist values (kTileAll: the value matrix)
     int32_t* pidx;         // partial shortlist rows (-1 = no row)
     int64_t ldo;           // kTileAll: row stride of the value matrix
@@ -75,7 +77,8 @@ struct FinArgs {
     int64_t ldx;
     int32_t d;
     int32_t metric;        // 0 = l2, 1 = l1
-    int32_t approx_mode;   // 0: values are ||x||^2 - 2 q.x (MFMA); 1: direct d^2 (l2) or rho (l1)
+    int32_t approx_mode;   // 0: ||x||^2 - 2 q.x (MFMA); 1: direct d^2 (l2) or rho (l1);
+                           // 2: ||x~||^2 - 2 q~.x~ on quantised rows
     const float* pval;
     const int32_t* pidx;
     int32_t nsplit;        // BF mode: lists of query q at (s * m + q) * C, s < nsplit
@@ -86,6 +89,9 @@ struct FinArgs {
     const uint32_t* xmax_bits;  // largest database row norm (float bits, approx_mode 0)
     const uint32_t* flags_q;    // value flags of Q and X (see tile_exact), may be null
     const uint32_t* flags_x;
+    const float* qerr;          // approx_mode 2 (quantised tile): ||q - q~|| per query,
+    const uint32_t* xerr_max_bits;  // and the largest ||x - x~|| (float bits)
+    float* out_approx;          // optional [m][k]: tile distance of each result before re-scoring
     const int64_t* id_map; // row of X -> reported id (nullptr: identity)
     int64_t* out_idx;      // [rows of Q][k]
     float* out_dist;
@@ -142,6 +148,18 @@ RBC_DECL_KS(5)
 RBC_DECL_KS(6)
 RBC_DECL_KS(7)
 RBC_DECL_KS(8)
+#define RBC_DECL_KB(n)                                                                     \
+    hipError_t launch_tile_lowp_kb##n(int fmt, int c, dim3 grid, const TileArgs& a,       \
+                                      hipStream_t st);
+RBC_DECL_KB(1)
+RBC_DECL_KB(2)
+RBC_DECL_KB(3)
+RBC_DECL_KB(4)
+// fmt 0: bf16 (kb = ceil(d / 32) feature blocks), 1: fp8 e4m3 (d <= 128)
+hipError_t launch_tile_lowp(int fmt, int kb, int c, dim3 grid, const TileArgs& a, hipStream_t st);
+hipError_t launch_quantize(int fmt, const float* A, int64_t rows, int64_t lda, int32_t d,
+                           float mult, void* out, int64_t ldo, int32_t dpad, float* norm2,
+                           float* err, uint8_t* scale_out, uint32_t* stat, hipStream_t st);
 hipError_t launch_finalize(int c, const FinArgs& a, hipStream_t st);
 hipError_t launch_exact(const ExactArgs& a, int grid, hipStream_t st);
 

@@ -13,6 +13,7 @@ namespace rbc {
 constexpr int kPathMfma = 0;   // L2 tile on the matrix cores
 constexpr int kPathValu = 1;   // l1 / small-d l2 tile on the vector ALUs
 constexpr int kPathExact = 2;  // exhaustive float64 (k or d beyond the tiles)
+constexpr int kPathLowp = 3;   // L2 tile on quantised rows (bf16 / fp8)
 constexpr int kConcurrentBlocks = 512;  // 256 CUs x 2 resident tile workgroups
 constexpr int kMaxSplits = 64;          // one partial list per lane in finalize
 constexpr int kFallbackBlocks = 256;
@@ -56,12 +57,17 @@ struct BfPlan {
     int32_t nqblk;     // 256-query blocks
     int32_t nsplit;    // database splits
     int32_t rps;       // rows per split (BF mode)
+    int prec;          // rbc_precision
+    int kb;            // low precision: 32-feature blocks (bf16) / 1 (fp8)
+    int dq;            // low precision: padded row length of the quantised copies
 };
 
 struct BfWork {
     int32_t* fb_list = nullptr;
     // [0] fallback count, [2] work queue, [4..7] query stats (see xstat),
-    // [8..11] database stats: [8] max row norm bits, [9..11] value flags
+    // [8..11] database stats: [8] max row norm bits, [9..11] value flags,
+    // [12..13] quantised database: max ||x~||, max ||x - x~||; [14..15] the
+    // same for the queries
     int32_t* counters = nullptr;
     float* Qp = nullptr;
     float* Xp = nullptr;
@@ -69,6 +75,11 @@ struct BfWork {
     float* xn = nullptr;
     float* pval = nullptr;
     int32_t* pidx = nullptr;
+    void* Qq = nullptr;        // quantised rows (low precision)
+    void* Xq = nullptr;
+    uint8_t* qscale = nullptr;
+    uint8_t* xscale = nullptr;
+    float* qerr = nullptr;
 };
 
 // Records a pair of HIP events around a launch when timing is enabled
@@ -91,10 +102,12 @@ void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w);
 // xstat: precomputed stats of X (with xn), or null to compute them.
 int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
            int64_t ldx, const float* xn, const uint32_t* xstat, const int64_t* id_map,
-           int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st);
+           int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats, hipStream_t st,
+           float* out_approx = nullptr);
 FinArgs fin_args(const BfPlan& p, const float* Qk, int64_t m, int64_t ldqk, const float* Xk,
                  int64_t ldxk, const uint32_t* xstat, const int64_t* id_map,
-                 int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats);
+                 int64_t* out_idx, float* out_dist, BfWork& w, int64_t* stats,
+                 float* out_approx = nullptr);
 int run_finalize(const BfPlan& p, const FinArgs& f, hipStream_t st);
 int run_fallback(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X,
                  int64_t n, int64_t ldx, const int64_t* id_map, int64_t* out_idx,

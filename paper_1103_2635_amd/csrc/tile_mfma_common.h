@@ -1,0 +1,249 @@
+// tile_mfma_common.h -- the matrix-core distance tile, generic over the
+// arithmetic of the contraction (fp32, bf16, fp8), shared by k_tile_mfma.hip
+// (fp32), k_tile_bf16.hip and k_tile_fp8.hip.
+//
+// Sec. 3 observes that the distance step of BF(Q, X) is shaped like a
+// matrix product.  For the Euclidean metric the ranking of database rows for
+// a fixed query q only needs  val(x) = ||x||^2 - 2 q.x  (||q||^2 is common to
+// all rows), a dense contraction over the d features.
+//
+// Layout of one wavefront's tile: rows of the 16x16 MFMA output are 32
+// database rows (two 16-row blocks), columns are the wavefront's 64 queries
+// (four 16-query blocks).  The first MFMA of each accumulator takes ||x||^2 as
+// its C operand and the query fragments carry the factor -2 (exact in every
+// format), so the MFMA result is val directly.  Which feature feeds which
+// k-slot of an MFMA is free as long as both operands agree: every lane loads
+// one contiguous run of features of its row per MFMA.  The database fragments
+// of the next 32 rows are loaded while the current ones are used.
+//
+// The comparison step (per-query top-c) needs one query per lane, so each
+// 32x64 block of results goes through a wavefront-private LDS tile (written as
+// [query][row], read back one query per lane), then every lane pushes its 32
+// values into a sorted register shortlist (TopC).
+//
+// A Policy provides
+//   QFrag / XFrag          fragment types of one lane,
+//   kBlocks                MFMAs per 16x16 output block (feature blocks),
+//   load_q(frag, base, f)  the query run for feature block f (already -2 q),
+//   load_x(frag, base, f)  the database run,
+//   mma(xf, qf, c)         one MFMA step.
+#pragma once
+
+#include "rbc_device.h"
+
+namespace rbc {
+
+constexpr int kTStride = 36;  // floats per query row of the transpose tile
+
+template <class P>
+__device__ __forceinline__ void load_xfrags(typename P::XFrag (&xa)[2][P::kBlocks],
+                                            const TileArgs& a, int base, int c16, int g) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        int row = base + 16 * rb + c16;
+        row = row < a.n ? row : a.n - 1;
+#pragma unroll
+        for (int f = 0; f < P::kBlocks; ++f) P::load_x(xa[rb][f], a, row, f, g);
+    }
+}
+
+template <class P>
+__device__ __forceinline__ void load_qfrags(typename P::QFrag (&qf)[4][P::kBlocks],
+                                            const TileArgs& a, const int (&qrow)[4], int g) {
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int f = 0; f < P::kBlocks; ++f) P::load_q(qf[qb][f], a, qrow[qb], f, g);
+}
+
+// The 32 x 64 values of rows [base, base + 32): acc[rb][qb][i] is row
+// base + 16 rb + 4 g + i, query 16 qb + c16 (+inf beyond r1).
+template <class P>
+__device__ __forceinline__ void tile_step(f4 (&acc)[2][4], const typename P::QFrag (&qf)[4][P::kBlocks],
+                                          const typename P::XFrag (&xa)[2][P::kBlocks],
+                                          const float* xn, int base, int r1, int g) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        f4 nv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = base + 16 * rb + 4 * g + i;
+            nv[i] = row < r1 ? xn[row] : RBC_INF;
+        }
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = P::mma(xa[rb][0], qf[qb][0], nv);
+    }
+#pragma unroll
+    for (int f = 1; f < P::kBlocks; ++f)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = P::mma(xa[rb][f], qf[qb][f], acc[rb][qb]);
+}
+
+// Scan database rows [r0, r1) for the wavefront's 64 queries; lanes with act
+// push their values into top.
+template <class P, int C>
+__device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[4][P::kBlocks],
+                                          const TileArgs& a, int r0, int r1, bool act,
+                                          TopC<C>& top, float* tb, int lane) {
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    typename P::XFrag xa[2][P::kBlocks];
+    load_xfrags<P>(xa, a, r0, c16, g);
+    for (int base = r0; base < r1; base += kRowsMfma) {
+        typename P::XFrag xb[2][P::kBlocks];
+        const int next = base + kRowsMfma;
+        load_xfrags<P>(xb, a, next < r1 ? next : base, c16, g);
+        f4 acc[2][4];
+        tile_step<P>(acc, qf, xa, a.xn, base, r1, g);
+        // transpose: element (query 16 qb + c16, row 16 rb + 4 g + i)
+        wave_lds_sync();
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+                *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
+        wave_lds_sync();
+        f4 vals[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) vals[t] = *(const f4*)(tb + lane * kTStride + 4 * t);
+        if (act) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int f = 0; f < P::kBlocks; ++f) xa[rb][f] = xb[rb][f];
+    }
+}
+
+// BF mode: grid (query blocks of 256, database splits).
+template <class P, int C>
+__device__ __forceinline__ void tile_bf_body(const TileArgs& a, float* tbuf_wave) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    const int slot0 = blockIdx.x * kTileQ + wave * kWave;
+    typename P::QFrag qf[4][P::kBlocks];
+    int qrow[4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+        const int slot = slot0 + 16 * qb + c16;
+        qrow[qb] = slot < a.m ? slot : a.m - 1;
+    }
+    load_qfrags<P>(qf, a, qrow, g);
+    const int myslot = slot0 + lane;
+    TopC<C> top;
+    top.init();
+    const int64_t r0 = (int64_t)blockIdx.y * a.rps;
+    const int64_t r1 = r0 + a.rps < a.n ? r0 + a.rps : a.n;
+    if (r0 < r1) scan_rows<P, C>(qf, a, (int)r0, (int)r1, myslot < a.m, top, tbuf_wave, lane);
+    if (myslot < a.m) {
+        const int64_t off = ((int64_t)blockIdx.y * a.m + myslot) * C;
+        top.store(a.pval + off, a.pidx + off);
+    }
+}
+
+// Item mode: persistent wavefronts, each taking (representative, 64-query
+// chunk) items from the queue until it is empty.  Wavefronts work
+// independently (no workgroup barrier); consecutive items usually belong to
+// the same representative, so co-resident wavefronts share its list rows in
+// the caches.
+template <class P, int C>
+__device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_wave) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    const int total = *a.item_total;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(a.item_queue, 1);
+        item = __shfl(item, 0);
+        if (item >= total) break;
+        const int r = item_rep(a, item);
+        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kWave;
+        const int q_end = a.roff[r + 1];
+        typename P::QFrag qf[4][P::kBlocks];
+        int qrow[4];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+            const int p = q_begin + 16 * qb + c16;
+            qrow[qb] = a.qlist[p < q_end ? p : q_end - 1];
+        }
+        load_qfrags<P>(qf, a, qrow, g);
+        const int p = q_begin + lane;
+        const bool valid = p < q_end;
+        const int q = a.qlist[valid ? p : q_end - 1];
+        TopC<C> top;
+        if (a.tau) top.seed(a.tau[q]); else top.init();
+        scan_rows<P, C>(qf, a, a.list_off[r], a.list_off[r + 1], valid, top, tbuf_wave, lane);
+        if (valid) {
+            const int64_t pair =
+                a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r] : (int64_t)q;
+            top.store(a.pval + pair * C, a.pidx + pair * C);
+        }
+        if (a.stats && lane == 0) {
+            const int nq = q_end - q_begin < kWave ? q_end - q_begin : kWave;
+            atomicAdd((unsigned long long*)&a.stats[2],
+                      (unsigned long long)nq * (a.list_off[r + 1] - a.list_off[r]));
+        }
+    }
+}
+
+// All mode: every value written out, out[q * ldo + row] (one-shot build).
+template <class P>
+__device__ __forceinline__ void tile_all_body(const TileArgs& a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    const int slot0 = blockIdx.x * kTileQ + wave * kWave;
+    typename P::QFrag qf[4][P::kBlocks];
+    int qrow[4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+        const int slot = slot0 + 16 * qb + c16;
+        qrow[qb] = slot < a.m ? slot : a.m - 1;
+    }
+    load_qfrags<P>(qf, a, qrow, g);
+    const int r0 = (int)((int64_t)blockIdx.y * a.rps);
+    const int r1 = (int)(r0 + (int64_t)a.rps < a.n ? r0 + a.rps : a.n);
+    if (r0 >= r1) return;
+    typename P::XFrag xa[2][P::kBlocks];
+    load_xfrags<P>(xa, a, r0, c16, g);
+    for (int base = r0; base < r1; base += kRowsMfma) {
+        typename P::XFrag xb[2][P::kBlocks];
+        const int next = base + kRowsMfma;
+        load_xfrags<P>(xb, a, next < r1 ? next : base, c16, g);
+        f4 acc[2][4];
+        tile_step<P>(acc, qf, xa, a.xn, base, r1, g);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int row = base + 16 * rb + 4 * g;
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) {
+                const int slot = slot0 + 16 * qb + c16;
+                if (slot >= a.m) continue;
+                float* op = a.pval + (int64_t)slot * a.ldo + row;
+                if (row + 3 < r1) {
+                    *(f4*)op = acc[rb][qb];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (row + i < r1) op[i] = acc[rb][qb][i];
+                }
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int f = 0; f < P::kBlocks; ++f) xa[rb][f] = xb[rb][f];
+    }
+}
+
+}  // namespace rbc

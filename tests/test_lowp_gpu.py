@@ -1,0 +1,80 @@
+"""GPU parity of the low-precision brute force (BF16 and FP8 e4m3 ranking
+tiles, FP32 re-score, FP64 near-ties, certificate): results must equal the
+oracle exactly like the FP32 path; the pre-re-score distances are checked
+against the quantisation bound and their error against FP64 is reported."""
+import numpy as np
+import pytest
+
+import datagen
+from knn_check import assert_knn_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rbc():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1103_2635_amd as rbc
+
+    rbc.lib()
+    return rbc
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run(rbc, Q, X, k, prec):
+    import torch
+
+    stats = rbc.new_stats()
+    approx = torch.full((Q.shape[0], k), float("nan"), device="cuda")
+    idx, dist = rbc.bf_search(_dev(Q), _dev(X), k, "l2", precision=prec, stats=stats,
+                              approx_dist=approx)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), dist.cpu().numpy(), approx.cpu().numpy(), stats.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("case", [("sub16", 60000, 400, 128), ("sub8", 50000, 300, 64),
+                                  ("iid16", 10000, 500, 16), ("zipf128", 30000, 200, 128)],
+                         ids=["sub16", "sub8", "iid16", "zipf128"])
+def test_lowp_bf_exact(rbc, orc, prec, case):
+    name, n, m, d = case
+    X, Q = datagen.database(name, n), datagen.queries(name, m)
+    for k in (1, 10):
+        idx, dist, approx, st = _run(rbc, Q, X, k, prec)
+        ref = orc.bf_knn(Q, X, k, "l2")
+        assert_knn_parity(idx, dist, Q, X, k, "l2", orc, ref=ref)
+        # pre-re-score distances: within the quantisation bound of the FP64 distance
+        got64 = orc.rho_pairs(np.repeat(Q, k, 0), X[idx.reshape(-1)], "l2").reshape(idx.shape)
+        ok = ~np.isnan(approx)
+        rel = np.abs(approx[ok] - got64[ok]) / np.maximum(got64[ok], 1e-30)
+        bound = {"bf16": 0.05, "fp8": 0.5}[prec]
+        assert rel.max() < bound, (prec, rel.max())
+        print("%s %s k=%d pre-re-score rel err max %.3g mean %.3g fallbacks %d" % (
+            prec, name, k, rel.max(), rel.mean(), st[0]))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_lowp_ragged_and_errors(rbc, orc, prec):
+    rng = np.random.default_rng(31)
+    for (n, m, d) in ((700, 130, 17), (2049, 65, 33), (300, 5, 100)):
+        X = rng.standard_normal((n, d)).astype(np.float32)
+        Q = rng.standard_normal((m, d)).astype(np.float32)
+        for k in (1, 7):
+            idx, dist, approx, st = _run(rbc, Q, X, k, prec)
+            assert_knn_parity(idx, dist, Q, X, k, "l2", orc)
+    import torch
+
+    Xd = torch.zeros((10, 200), device="cuda")
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.bf_search(Xd[:2], Xd, 1, precision=prec)  # d > 128
+    assert e.value.status == -4
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.bf_search(Xd[:2, :16].contiguous(), Xd[:, :16].contiguous(), 1, "l1", precision=prec)
+    assert e.value.status == -4
