@@ -55,6 +55,9 @@ def main():
                     help="queries of the oracle's timed search sample (0: skip the CPU baseline)")
     ap.add_argument("--extra", action="store_true",
                     help="also time the other metric / k combinations")
+    ap.add_argument("--serving", action="store_true",
+                    help="also run the serving workload (resident 2M x 96 index, Poisson "
+                         "arrivals at three rates) and report p50/p99 latency and QPS")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -199,6 +202,8 @@ def main():
                          "%d queries (%.1f s), scaled to the %d-query job" % (
                              n, t_build, samp, m, t_search, m)}
 
+    serving = run_serving(rbc, torch, dev) if args.serving else None
+
     line = {
         "metric": "exact k-NN queries/s (n=1M, d=64), RBC build+search vs BF, recall 1.0",
         "value": round(m / ms_step * 1e3, 1),
@@ -233,7 +238,59 @@ def main():
     }
     if extra:
         line["paths"] = extra
+    if serving:
+        line["serving"] = serving
     print(json.dumps(line))
+
+
+def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32",)):
+    """Serving workload: resident exact index over n=2,000,000 d=96 (12-dim
+    subspace + N(0,0.01^2)), n_r=1,414; a 200,000-query pool; request sizes
+    round(exp(N(4, 1.5^2))) clipped to [1, 4096], k uniform in {1, 10};
+    Poisson arrivals at 0.3, 0.6, 0.9 of the measured saturation rate; four
+    execution streams, batches of at most 4,096 queries."""
+    import numpy as np
+
+    import datagen
+    from paper_1103_2635_amd.serving import GpuExecutor, Request, Scheduler, latency_stats, replay
+
+    w = datagen.WORKLOADS["sub12"]
+    X = torch.from_numpy(datagen.database("sub12")).to(dev)
+    pool = torch.from_numpy(datagen.queries("sub12")).to(dev)
+    reps = datagen.representatives("sub12")
+    ix = rbc.rbc_build(X, w.n_r, rep_idx=reps)
+    out = {"workload": "sub12: n=2,000,000 d=96, n_r=1,414, pool 200,000, sizes lognormal(4,1.5) "
+                       "clipped [1,4096], k in {1,10}, 4 streams, max batch 4096"}
+    for prec in precisions:
+        def search(Q, k, o, ws, prec=prec):
+            rbc.rbc_search(ix, Q, k, out=o, workspace=ws, precision=prec)
+
+        def ws_fn(m, k, prec=prec):
+            return rbc.rbc_search_workspace_size(ix, m, k, precision=prec)
+
+        res = {}
+        # saturation: every request of a trace arrives at once
+        t, sizes, ks, offs = datagen.arrival_trace("sub12", 1.0, n_requests, pool.shape[0])
+        def run(times):
+            ex = GpuExecutor(pool, search, ws_fn, 4)
+            sched = Scheduler(ex, 4, mem_budget=8 << 30, max_batch=4096)
+            reqs = [Request(i, int(offs[i]), int(sizes[i]), int(ks[i]), float(times[i]))
+                    for i in range(len(times))]
+            done = replay(sched, reqs, time.perf_counter, lambda s: time.sleep(0))
+            torch.cuda.synchronize()
+            return latency_stats(done)
+        run(np.zeros(200))  # warm-up of streams and allocator
+        sat = run(np.zeros(n_requests))
+        res["saturation_qps"] = round(sat["qps"], 1)
+        mean_size = float(np.mean(sizes))
+        for frac in (0.3, 0.6, 0.9):
+            rate = frac * sat["qps"] / mean_size
+            tt, _, _, _ = datagen.arrival_trace("sub12", rate, n_requests, pool.shape[0])
+            st = run(tt)
+            res["load_%.1f" % frac] = {k2: round(v, 3) for k2, v in st.items()}
+        out[prec] = res
+    ix.free()
+    return out
 
 
 if __name__ == "__main__":

@@ -478,6 +478,8 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
 
 int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
                 const rbc_search_opts* opts, BfPlan* p) {
+    if (opts && opts->precision != RBC_FP32)
+        return set_err(RBC_EUNSUPPORTED, "rbc_search: only RBC_FP32 is implemented");
     if (ix->mode == RBC_ONESHOT && k > ix->s)
         return set_err(RBC_EINVAL, "one-shot search needs k <= s (%lld)", (long long)ix->s);
     if (ix->mode == RBC_EXACT && (int64_t)m * ix->n_r >= ((int64_t)1 << 31))

@@ -1,0 +1,63 @@
+"""Serving on the GPU: a resident exact index, an open-loop trace of requests
+of lognormal sizes and k in {1, 10}, four execution streams, continuous
+batching.  Every request's result must be identical to the same request
+searched alone, and a sample must match the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import datagen
+from knn_check import assert_knn_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_alone(orc):
+    import torch
+
+    import paper_1103_2635_amd as rbc
+    from paper_1103_2635_amd.serving import GpuExecutor, Request, Scheduler, latency_stats, replay
+
+    n, n_r, pool_n = 200_000, 447, 20_000
+    X = datagen.database("sub12", n)
+    pool = datagen.queries("sub12", pool_n)
+    reps = datagen.representatives("sub12", n, n_r)
+    Xd, Pd = torch.from_numpy(X).cuda(), torch.from_numpy(pool).cuda()
+    ix = rbc.rbc_build(Xd, n_r, rep_idx=reps)
+
+    def search(Q, k, out, ws):
+        rbc.rbc_search(ix, Q, k, out=out, workspace=ws)
+
+    def ws_fn(m, k):
+        return rbc.rbc_search_workspace_size(ix, m, k)
+
+    ex = GpuExecutor(Pd, search, ws_fn, 4)
+    sched = Scheduler(ex, 4, mem_budget=3 << 30, max_batch=1024)
+    rng = np.random.default_rng(7)
+    nreq = 250
+    sizes = np.clip(np.rint(np.exp(rng.normal(4, 1.5, nreq))), 1, 2048).astype(int)
+    ks = np.where(rng.random(nreq) < 0.5, 1, 10)
+    offs = rng.integers(0, pool_n - 2048, nreq)
+    arr = np.cumsum(rng.exponential(1 / 800.0, nreq))
+    reqs = [Request(i, int(offs[i]), int(sizes[i]), int(ks[i]), float(arr[i])) for i in range(nreq)]
+    done = replay(sched, reqs, time.perf_counter, lambda s: time.sleep(0))
+    torch.cuda.synchronize()
+    assert len(done) == nreq
+    st = latency_stats(done)
+    print("served %d requests, p50 %.2f ms p99 %.2f ms, %d batches, max concurrent %d" % (
+        nreq, st["p50_ms"], st["p99_ms"], sched.batches_launched, sched.max_concurrent))
+    assert sched.batches_launched < sum((r.m + 1023) // 1024 for r in reqs) or sched.max_concurrent > 1
+    checked = 0
+    for r in done:
+        parts = sorted(r.results, key=lambda x: x[0])
+        idx = torch.cat([p[1] for p in parts]).cpu().numpy()
+        dist = torch.cat([p[2] for p in parts]).cpu().numpy()
+        ai, ad = rbc.rbc_search(ix, Pd[r.offset:r.offset + r.m], r.k)
+        torch.cuda.synchronize()
+        assert np.array_equal(idx, ai.cpu().numpy()), r.rid
+        assert np.array_equal(dist, ad.cpu().numpy()), r.rid
+        if checked < 6:
+            q = pool[r.offset:r.offset + min(r.m, 20)]
+            assert_knn_parity(idx[:q.shape[0]], dist[:q.shape[0]], q, X, r.k, "l2", orc)
+            checked += 1
