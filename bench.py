@@ -243,7 +243,7 @@ def main():
     print(json.dumps(line))
 
 
-def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32",)):
+def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32", "bf16")):
     """Serving workload: resident exact index over n=2,000,000 d=96 (12-dim
     subspace + N(0,0.01^2)), n_r=1,414; a 200,000-query pool; request sizes
     round(exp(N(4, 1.5^2))) clipped to [1, 4096], k uniform in {1, 10};
@@ -258,7 +258,7 @@ def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32",)):
     X = torch.from_numpy(datagen.database("sub12")).to(dev)
     pool = torch.from_numpy(datagen.queries("sub12")).to(dev)
     reps = datagen.representatives("sub12")
-    ix = rbc.rbc_build(X, w.n_r, rep_idx=reps)
+    ix = rbc.rbc_build(X, w.n_r, rep_idx=reps, precisions=precisions)
     out = {"workload": "sub12: n=2,000,000 d=96, n_r=1,414, pool 200,000, sizes lognormal(4,1.5) "
                        "clipped [1,4096], k in {1,10}, 4 streams, max batch 4096"}
     for prec in precisions:

@@ -106,6 +106,11 @@ typedef struct rbc_build_params {
     uint64_t seed;           /* seed of the representative draw when rep_idx is NULL */
     const int64_t* rep_idx;  /* optional HOST array of n_r distinct row ids of X;
                                 copied and sorted ascending by the library */
+    int32_t precisions;      /* bit mask (1 << rbc_precision) of the low precisions that
+                                rbc_search may use on this index (exact mode, RBC_L2,
+                                d <= 128): their quantised copies of the rows are built
+                                with the index; 0 = fp32 only */
+    int32_t reserved;
 } rbc_build_params;
 
 typedef struct rbc_index rbc_index; /* opaque; owns its device memory */
@@ -162,6 +167,11 @@ int rbc_build(const float* X, int64_t n, int64_t ldx, int32_t d,
  *   of at least rbc_search_workspace_size() bytes.  Concurrent calls on
  *   different streams with different workspaces are safe (the index is
  *   read-only after rbc_build).
+ *   opts->precision RBC_BF16 / RBC_FP8_E4M3 ranks the kept lists with the
+ *   quantised rows built into an exact index (rbc_build_params.precisions);
+ *   the answers stay exact (float32 re-score, certificate that includes the
+ *   quantisation error, float64 fallback).  RBC_EUNSUPPORTED when the index
+ *   holds no copy in that precision or is a one-shot index.
  */
 int rbc_search_workspace_size(const rbc_index* index, int64_t m, int64_t ldq, int32_t k,
                               const rbc_search_opts* opts, size_t* bytes);

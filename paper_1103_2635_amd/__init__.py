@@ -39,7 +39,8 @@ class SearchOpts(ctypes.Structure):
 
 class BuildParams(ctypes.Structure):
     _fields_ = [("mode", _I32), ("metric", _I32), ("n_r", _I64), ("s", _I64),
-                ("seed", ctypes.c_uint64), ("rep_idx", _P)]
+                ("seed", ctypes.c_uint64), ("rep_idx", _P), ("precisions", _I32),
+                ("reserved", _I32)]
 
 
 class RbcError(RuntimeError):
@@ -205,8 +206,9 @@ class Index:
             pass
 
 
-def rbc_build(X, n_r, mode="exact", metric="l2", s=0, seed=0, rep_idx=None):
-    """Build an RBC index over X (rep_idx: optional host int64 array of ids)."""
+def rbc_build(X, n_r, mode="exact", metric="l2", s=0, seed=0, rep_idx=None, precisions=()):
+    """Build an RBC index over X (rep_idx: optional host int64 array of ids;
+    precisions: low precisions ("bf16", "fp8") rbc_search may use)."""
     import numpy as np
 
     _mat(X, "X")
@@ -217,6 +219,7 @@ def rbc_build(X, n_r, mode="exact", metric="l2", s=0, seed=0, rep_idx=None):
     p.n_r = int(n_r)
     p.s = int(s)
     p.seed = int(seed)
+    p.precisions = sum(1 << _PRECS[pr] for pr in set(precisions) if _PRECS[pr] != FP32)
     reps = None
     if rep_idx is not None:
         reps = np.ascontiguousarray(rep_idx, dtype=np.int64)

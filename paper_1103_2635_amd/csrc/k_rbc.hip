@@ -626,10 +626,14 @@ hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_
 //        gc^2 - ||q||^2 + 2 E,  E = 4 (d + 2) u (||q|| + max ||x||)^2
 //   mode 1 (direct l2, values d^2):  gc^2 (1 + delta)
 //   mode 2 (direct l1, values rho):  gc (1 + delta)
+//   mode 3 (matrix core on quantised rows, ||x~||^2 - 2 q~.x~): a row within
+//        gc of q is within gc + ||q - q~|| + max ||x - x~|| of q~, so
+//        (gc + e_q + e_x)^2 - ||q~||^2 + 2 E with E on the quantised norms
 // each widened by a relative 4e-6; +inf when gc is.
 __global__ void tau_kernel(const float* gcup, const float* qn, const uint32_t* xmax_bits,
                            const uint32_t* flags_q, const uint32_t* flags_x, int32_t m, int32_t d,
-                           int32_t mode, double delta, float* tau) {
+                           int32_t mode, double delta, const float* qerr,
+                           const uint32_t* xerr_bits, float* tau) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= m) return;
     const double gc = (double)gcup[q];
@@ -643,6 +647,12 @@ __global__ void tau_kernel(const float* gcup, const float* qn, const uint32_t* x
                                  ? 0.0
                                  : 4.0 * (d + 2) * 5.9604644775390625e-8 * sq * sq;
             v = gc * gc * (1.0 + 4e-6) - n2 + 2.0 * e;
+        } else if (mode == 3) {
+            const double n2 = (double)qn[q];
+            const double sq = __builtin_sqrt(n2) + (double)__uint_as_float(*xmax_bits);
+            const double e = 4.0 * (d + 2) * 5.9604644775390625e-8 * sq * sq;
+            const double g = gc + (double)qerr[q] + (double)__uint_as_float(*xerr_bits);
+            v = g * g * (1.0 + 4e-6) - n2 + 2.0 * e;
         } else if (mode == 1) {
             v = gc * gc * (1.0 + delta) * (1.0 + 4e-6);
         } else {
@@ -655,9 +665,10 @@ __global__ void tau_kernel(const float* gcup, const float* qn, const uint32_t* x
 
 hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits,
                       const uint32_t* flags_q, const uint32_t* flags_x, int32_t m, int32_t d,
-                      int32_t mode, double delta, float* tau, hipStream_t st) {
+                      int32_t mode, double delta, float* tau, hipStream_t st, const float* qerr,
+                      const uint32_t* xerr_bits) {
     hipLaunchKernelGGL(tau_kernel, dim3((m + 255) / 256), dim3(256), 0, st, gcup, qn, xmax_bits,
-                       flags_q, flags_x, m, d, mode, delta, tau);
+                       flags_q, flags_x, m, d, mode, delta, qerr, xerr_bits, tau);
     return hipGetLastError();
 }
 

@@ -72,24 +72,43 @@ __global__ __launch_bounds__(256, 2) void tile_fp8(TileArgs a) {
     tile_bf_body<Fp8Policy, C>(a, tbuf[threadIdx.x >> 6]);
 }
 
+template <int KB, int C>
+__global__ __launch_bounds__(256, 2) void tile_bf16_items(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
+    tile_items_body<Bf16Policy<KB>, C>(a, tbuf[threadIdx.x >> 6]);
+}
+
 template <int C>
-static hipError_t launch_c(int fmt, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (fmt == 0)
-        hipLaunchKernelGGL((tile_bf16<RBC_KB, C>), grid, dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((tile_fp8<C>), grid, dim3(256), 0, st, a);
+__global__ __launch_bounds__(256, 2) void tile_fp8_items(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
+    tile_items_body<Fp8Policy, C>(a, tbuf[threadIdx.x >> 6]);
+}
+
+template <int C>
+static hipError_t launch_c(int fmt, int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
+    if (fmt == 0) {
+        if (mode == kTileItems)
+            hipLaunchKernelGGL((tile_bf16_items<RBC_KB, C>), grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((tile_bf16<RBC_KB, C>), grid, dim3(256), 0, st, a);
+    } else {
+        if (mode == kTileItems)
+            hipLaunchKernelGGL((tile_fp8_items<C>), grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((tile_fp8<C>), grid, dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
-hipError_t RBC_CAT(launch_tile_lowp_kb, RBC_KB)(int fmt, int c, dim3 grid, const TileArgs& a,
-                                                hipStream_t st) {
+hipError_t RBC_CAT(launch_tile_lowp_kb, RBC_KB)(int fmt, int c, int mode, dim3 grid,
+                                                const TileArgs& a, hipStream_t st) {
     if (fmt == 1 && RBC_KB != 1) return hipErrorInvalidValue;  // fp8 kernels live in the KB = 1 object
     switch (c) {
-        case 4: return launch_c<4>(fmt, grid, a, st);
-        case 8: return launch_c<8>(fmt, grid, a, st);
-        case 16: return launch_c<16>(fmt, grid, a, st);
-        case 32: return launch_c<32>(fmt, grid, a, st);
-        case 64: return launch_c<64>(fmt, grid, a, st);
+        case 4: return launch_c<4>(fmt, mode, grid, a, st);
+        case 8: return launch_c<8>(fmt, mode, grid, a, st);
+        case 16: return launch_c<16>(fmt, mode, grid, a, st);
+        case 32: return launch_c<32>(fmt, mode, grid, a, st);
+        case 64: return launch_c<64>(fmt, mode, grid, a, st);
     }
     return hipErrorInvalidValue;
 }

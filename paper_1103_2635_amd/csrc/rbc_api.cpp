@@ -155,7 +155,7 @@ int run_bf_lowp(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const f
     {
         KernelTimer kt("tile", st);
         const dim3 grid(p.nqblk, p.nsplit);
-        if ((rc = hip_status(launch_tile_lowp(fmt, p.kb, p.c, grid, a, st), "tile (low precision)")))
+        if ((rc = hip_status(launch_tile_lowp(fmt, p.kb, p.c, kTileBF, grid, a, st), "tile (low precision)")))
             return rc;
     }
     FinArgs f = fin_args(p, Q, m, ldq, X, ldx, ctr + 12, id_map, out_idx, out_dist, w, stats,

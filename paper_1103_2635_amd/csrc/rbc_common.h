@@ -149,14 +149,15 @@ RBC_DECL_KS(6)
 RBC_DECL_KS(7)
 RBC_DECL_KS(8)
 #define RBC_DECL_KB(n)                                                                     \
-    hipError_t launch_tile_lowp_kb##n(int fmt, int c, dim3 grid, const TileArgs& a,       \
-                                      hipStream_t st);
+    hipError_t launch_tile_lowp_kb##n(int fmt, int c, int mode, dim3 grid,                 \
+                                      const TileArgs& a, hipStream_t st);
 RBC_DECL_KB(1)
 RBC_DECL_KB(2)
 RBC_DECL_KB(3)
 RBC_DECL_KB(4)
 // fmt 0: bf16 (kb = ceil(d / 32) feature blocks), 1: fp8 e4m3 (d <= 128)
-hipError_t launch_tile_lowp(int fmt, int kb, int c, dim3 grid, const TileArgs& a, hipStream_t st);
+hipError_t launch_tile_lowp(int fmt, int kb, int c, int mode, dim3 grid, const TileArgs& a,
+                            hipStream_t st);
 hipError_t launch_quantize(int fmt, const float* A, int64_t rows, int64_t lda, int32_t d,
                            float mult, void* out, int64_t ldo, int32_t dpad, float* norm2,
                            float* err, uint8_t* scale_out, uint32_t* stat, hipStream_t st);

@@ -34,13 +34,14 @@ hipError_t launch_tile_valu(int metric, int ks, int c, int mode, dim3 grid,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tile_lowp(int fmt, int kb, int c, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (fmt == 1) return launch_tile_lowp_kb1(fmt, c, grid, a, st);
+hipError_t launch_tile_lowp(int fmt, int kb, int c, int mode, dim3 grid, const TileArgs& a,
+                            hipStream_t st) {
+    if (fmt == 1) return launch_tile_lowp_kb1(fmt, c, mode, grid, a, st);
     switch (kb) {
-        case 1: return launch_tile_lowp_kb1(fmt, c, grid, a, st);
-        case 2: return launch_tile_lowp_kb2(fmt, c, grid, a, st);
-        case 3: return launch_tile_lowp_kb3(fmt, c, grid, a, st);
-        case 4: return launch_tile_lowp_kb4(fmt, c, grid, a, st);
+        case 1: return launch_tile_lowp_kb1(fmt, c, mode, grid, a, st);
+        case 2: return launch_tile_lowp_kb2(fmt, c, mode, grid, a, st);
+        case 3: return launch_tile_lowp_kb3(fmt, c, mode, grid, a, st);
+        case 4: return launch_tile_lowp_kb4(fmt, c, mode, grid, a, st);
     }
     return hipErrorInvalidValue;
 }

@@ -36,6 +36,14 @@ struct rbc_index {
     float* R = nullptr;          // representatives, n_r x ld
     double* psi = nullptr;       // list radii
     uint32_t* norms_max = nullptr;  // xstat of Xp: [0] max row norm bits, [1..3] value flags
+    // quantised copies of Xp for low-precision searches, indexed by rbc_precision
+    struct Quant {
+        void* X = nullptr;        // rows x dq elements (bf16) or bytes (fp8 e4m3)
+        float* xn = nullptr;      // ||x~||^2
+        uint8_t* scale = nullptr; // fp8: E8M0 row scales
+        uint32_t* stat = nullptr; // [0] max ||x~||, [1] max ||x - x~|| (float bits)
+        int dq = 0;
+    } quant[3];
     std::vector<int64_t> rep_host;
     std::vector<void*> allocs;
     size_t bytes = 0;
@@ -320,6 +328,32 @@ int build_oneshot(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     return check(hipStreamSynchronize(st), "build");
 }
 
+// Quantised copies of the index rows for the requested low precisions.
+int build_quant(rbc_index* ix, int32_t precisions, hipStream_t st) {
+    if (precisions & ~((1 << RBC_BF16) | (1 << RBC_FP8_E4M3)))
+        return set_err(RBC_EINVAL, "unknown bits in precisions");
+    if (ix->mode != RBC_EXACT || ix->metric != RBC_L2 || ix->d > 128)
+        return set_err(RBC_EUNSUPPORTED, "low precision needs an exact L2 index with d <= 128");
+    int rc;
+    for (int prec : {RBC_BF16, RBC_FP8_E4M3}) {
+        if (!(precisions & (1 << prec))) continue;
+        rbc_index::Quant& q = ix->quant[prec];
+        const int fmt = prec == RBC_BF16 ? 0 : 1;
+        q.dq = prec == RBC_BF16 ? (ix->d + 31) / 32 * 32 : 128;
+        uint8_t* xq = nullptr;
+        if ((rc = dev_alloc(ix, &xq, ix->rows * q.dq * (prec == RBC_BF16 ? 2 : 1)))) return rc;
+        q.X = xq;
+        if ((rc = dev_alloc(ix, &q.xn, ix->rows))) return rc;
+        if ((rc = dev_alloc(ix, &q.stat, 4))) return rc;
+        if (prec == RBC_FP8_E4M3 && (rc = dev_alloc(ix, &q.scale, ix->rows))) return rc;
+        if ((rc = check(launch_fill_i32((int32_t*)q.stat, 4, 0, st), "clear"))) return rc;
+        if ((rc = check(launch_quantize(fmt, ix->Xp, ix->rows, ix->ld, ix->d, 1.0f, q.X, q.dq, q.dq,
+                                        q.xn, nullptr, q.scale, q.stat, st), "quantize")))
+            return rc;
+    }
+    return check(hipStreamSynchronize(st), "quantize");
+}
+
 struct SearchWork {
     BfWork bf;
     float* DR = nullptr;       // stage-1 distances, m x ldd
@@ -461,7 +495,12 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
     w->bf.fb_list = cv.take<int32_t>(m);
     w->bf.counters = cv.take<int32_t>(kCounters);
     if (p.repack_q) w->bf.Qp = cv.take<float>(m * p.ldp);
-    if (p.path == kPathMfma) w->bf.qn = cv.take<float>(m);
+    if (p.path == kPathMfma || p.path == kPathLowp) w->bf.qn = cv.take<float>(m);
+    if (p.path == kPathLowp) {
+        w->bf.Qq = cv.take<uint8_t>(m * p.dq * (p.prec == RBC_BF16 ? 2 : 1));
+        w->bf.qerr = cv.take<float>(m);
+        if (p.prec == RBC_FP8_E4M3) w->bf.qscale = cv.take<uint8_t>(m);
+    }
     w->bf.pval = cv.take<float>(m * nr * p.c);
     w->bf.pidx = cv.take<int32_t>(m * nr * p.c);
     w->DR = cv.take<float>(m * stage1_ld(nr));
@@ -478,8 +517,12 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
 
 int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
                 const rbc_search_opts* opts, BfPlan* p) {
-    if (opts && opts->precision != RBC_FP32)
-        return set_err(RBC_EUNSUPPORTED, "rbc_search: only RBC_FP32 is implemented");
+    if (opts && opts->precision != RBC_FP32) {
+        const int pr = opts->precision;
+        if (ix->mode != RBC_EXACT || pr < 0 || pr > 2 || ix->quant[pr].X == nullptr)
+            return set_err(RBC_EUNSUPPORTED,
+                           "rbc_search precision %d needs an exact index built with it", pr);
+    }
     if (ix->mode == RBC_ONESHOT && k > ix->s)
         return set_err(RBC_EINVAL, "one-shot search needs k <= s (%lld)", (long long)ix->s);
     if (ix->mode == RBC_EXACT && (int64_t)m * ix->n_r >= ((int64_t)1 << 31))
@@ -493,6 +536,57 @@ int validate_search(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k) {
     if (rc) return rc;
     if (ldq < ix->d) return set_err(RBC_EINVAL, "ldq smaller than d");
     return RBC_OK;
+}
+
+// Stage 2 and finalize of the exact search on the quantised index rows.
+int search_exact_lowp(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m,
+                      int64_t ldq, int64_t* out_idx, float* out_dist, SearchWork& w,
+                      int64_t* stats, hipStream_t st) {
+    const rbc_index::Quant& qc = ix->quant[p.prec];
+    const int32_t nr = (int32_t)ix->n_r;
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = (const float*)w.bf.Qq;
+    a.ldq = p.dq;
+    a.m = (int32_t)m;
+    a.X = (const float*)qc.X;
+    a.ldx = qc.dq;
+    a.n = (int32_t)ix->rows;
+    a.d = ix->d;
+    a.xn = qc.xn;
+    a.qscale = w.bf.qscale;
+    a.xscale = qc.scale;
+    a.item_total = w.ioff + nr;
+    a.item_queue = w.bf.counters + 2;
+    a.ioff = w.ioff;
+    a.roff = w.roff;
+    a.qlist = w.qlist;
+    a.list_off = ix->list_off;
+    a.lrank = w.lrank;
+    a.qoff = w.qoff;
+    a.tau = w.tau;
+    a.n_r = nr;
+    a.pval = w.bf.pval;
+    a.pidx = w.bf.pidx;
+    a.stats = stats;
+    int rc;
+    {
+        KernelTimer kt("tile_items", st);
+        if ((rc = check(launch_tile_lowp(p.prec == RBC_BF16 ? 0 : 1, p.kb, p.c, kTileItems,
+                                         dim3(kItemBlocks), a, st), "stage 2 (low precision)")))
+            return rc;
+    }
+    FinArgs f = fin_args(p, Q, m, ldq, ix->Xp, ix->ld, qc.stat, ix->ids, out_idx, out_dist, w.bf,
+                         stats);
+    f.qoff = w.qoff;
+    f.npairs = w.npairs;
+    f.qerr = w.bf.qerr;
+    f.xerr_max_bits = qc.stat + 1;
+    f.flags_q = nullptr;
+    f.flags_x = nullptr;
+    if ((rc = run_finalize(p, f, st))) return rc;
+    return run_fallback(p, Q, m, ldq, ix->Xp, ix->rows, ix->ld, ix->ids, out_idx, out_dist, w.bf,
+                        st);
 }
 
 // Exact search, Sec. 5.2: stage 1 (all representative distances), pruning,
@@ -533,20 +627,34 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                                        hipMemcpyDeviceToDevice, st), "copy counts")))
             return rc;
         if ((rc = check(launch_scan_total(w.qoff, m, st), "pair offsets"))) return rc;
-        const int32_t isize = p.path == kPathMfma ? kWave : kTileQ;
+        const int32_t isize = p.path == kPathValu ? kTileQ : kWave;
         if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, isize, w.roff, w.ioff, w.qlist,
                                         st), "work list")))
             return rc;
+        if (p.path == kPathLowp) {
+            const rbc_index::Quant& qc = ix->quant[p.prec];
+            uint32_t* ctr = (uint32_t*)w.bf.counters;
+            if ((rc = check(launch_quantize(p.prec == RBC_BF16 ? 0 : 1, Q, m, ldq, p.d, -2.0f,
+                                            w.bf.Qq, p.dq, p.dq, w.bf.qn, w.bf.qerr, w.bf.qscale,
+                                            ctr + 14, st), "quantize Q")))
+                return rc;
+            if ((rc = check(launch_tau(w.gcup, w.bf.qn, qc.stat, nullptr, nullptr, (int32_t)m,
+                                       ix->d, 3, delta, w.tau, st, w.bf.qerr, qc.stat + 1),
+                            "thresholds")))
+                return rc;
+        }
         if (p.path == kPathMfma &&
             (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st,
                                          (uint32_t*)w.bf.counters + 5), "norms Q")))
             return rc;
         const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
-        if ((rc = check(launch_tau(w.gcup, w.bf.qn, ix->norms_max,
+        if (p.path != kPathLowp &&
+            (rc = check(launch_tau(w.gcup, w.bf.qn, ix->norms_max,
                                    (const uint32_t*)w.bf.counters + 5, ix->norms_max + 1,
                                    (int32_t)m, ix->d, mode, delta, w.tau, st), "thresholds")))
             return rc;
     }
+    if (p.path == kPathLowp) return search_exact_lowp(ix, p, Q, m, ldq, out_idx, out_dist, w, stats, st);
     TileArgs a;
     std::memset(&a, 0, sizeof(a));
     a.Q = Qk;
@@ -638,6 +746,7 @@ int rbc_build(const float* X, int64_t n, int64_t ldx, int32_t d, const rbc_build
         ix->rep_host = std::move(reps);
         rc = ix->mode == RBC_EXACT ? build_exact(ix, X, ldx, (hipStream_t)hip_stream)
                                    : build_oneshot(ix, X, ldx, (hipStream_t)hip_stream);
+        if (!rc && prm->precisions) rc = build_quant(ix, prm->precisions, (hipStream_t)hip_stream);
         if (rc) {
             free_index(ix);
             return rc;

@@ -53,7 +53,8 @@ hipError_t launch_worklist(const uint8_t* keep_rq, int32_t m, int32_t nr, int32_
 hipError_t launch_scan_total(int32_t* v, int64_t n, hipStream_t st);
 hipError_t launch_tau(const float* gcup, const float* qn, const uint32_t* xmax_bits,
                       const uint32_t* flags_q, const uint32_t* flags_x, int32_t m, int32_t d,
-                      int32_t mode, double delta, float* tau, hipStream_t st);
+                      int32_t mode, double delta, float* tau, hipStream_t st,
+                      const float* qerr = nullptr, const uint32_t* xerr_bits = nullptr);
 
 // One-shot build, per chunk of `reps` representatives whose values (tile
 // value space given by mode) are V[rep][0 .. n): candidate rows of each list.

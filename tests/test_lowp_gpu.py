@@ -78,3 +78,56 @@ def test_lowp_ragged_and_errors(rbc, orc, prec):
     with pytest.raises(rbc.RbcError) as e:
         rbc.bf_search(Xd[:2, :16].contiguous(), Xd[:, :16].contiguous(), 1, "l1", precision=prec)
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("case", [("sub8", 60000, 700, 64, 245), ("iid16", 20000, 300, 16, 141),
+                                  ("zipf128", 30000, 260, 128, 173)],
+                         ids=["sub8", "iid16", "zipf128"])
+def test_lowp_rbc_exact_search(rbc, orc, prec, case):
+    """Exact RBC search (Sec. 5.2) with the low-precision stage-2 tile: same
+    answers as the oracle's BF(Q, X) and as the FP32 search of the same index."""
+    import torch
+
+    name, n, m, d, n_r = case
+    X, Q = datagen.database(name, n), datagen.queries(name, m)
+    Xd, Qd = _dev(X), _dev(Q)
+    ix = rbc.rbc_build(Xd, n_r, seed=5, precisions=(prec,))
+    try:
+        for k in (1, 10):
+            stats = rbc.new_stats()
+            idx, dist = rbc.rbc_search(ix, Qd, k, precision=prec, stats=stats)
+            i32, d32 = rbc.rbc_search(ix, Qd, k)
+            torch.cuda.synchronize()
+            idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+            ref = orc.bf_knn(Q, X, k, "l2")
+            assert_knn_parity(idx, dist, Q, X, k, "l2", orc, ref=ref)
+            np.testing.assert_array_equal(idx, i32.cpu().numpy())
+            # the float32 re-score splits each sum over 64 / c lanes, so the
+            # two shortlist lengths may round differently (last bit)
+            np.testing.assert_allclose(dist, d32.cpu().numpy(), rtol=1e-6, atol=0)
+            st = stats.cpu().numpy()
+            print("rbc %s %s k=%d fallbacks %d pairs %d" % (prec, name, k, st[0], st[2]))
+    finally:
+        ix.free()
+
+
+def test_lowp_rbc_errors(rbc):
+    import torch
+
+    X = torch.randn((3000, 32), device="cuda")
+    ix = rbc.rbc_build(X, 50, seed=1, precisions=("bf16",))
+    try:
+        with pytest.raises(rbc.RbcError) as e:   # index holds no fp8 copy
+            rbc.rbc_search(ix, X[:10], 1, precision="fp8")
+        assert e.value.status == -4
+        idx, _ = rbc.rbc_search(ix, X[:10], 1, precision="bf16")
+        assert idx[:, 0].cpu().tolist() == list(range(10))
+    finally:
+        ix.free()
+    with pytest.raises(rbc.RbcError) as e:   # one-shot indexes are FP32 only
+        rbc.rbc_build(X, 50, mode="oneshot", s=64, seed=1, precisions=("bf16",))
+    assert e.value.status == -4
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.rbc_build(torch.randn((500, 16), device="cuda"), 20, metric="l1", precisions=("fp8",))
+    assert e.value.status == -4
