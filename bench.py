@@ -33,6 +33,32 @@ FP32_MFMA_PEAK_TF = 157.3   # MI355X dense fp32 matrix peak
 ALU_PEAK_TOPS = 78.6        # fp32 VALU lane-operations per second (157.3 TFLOP/s counts an FMA as 2)
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's counts), or None when
+    there is no summary or the kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            line = line.strip()
+            if not (line.startswith("{") and '"traffic_bytes"' in line):
+                continue
+            rec = json.loads(line)
+            if rec.get("kernel") != kernel:
+                continue
+            h = hashlib.sha256()
+            try:
+                for f in rec["sources"]:
+                    with open(os.path.join(ROOT, f), "rb") as fh:
+                        h.update(fh.read())
+            except OSError:
+                return None
+            return rec["traffic_bytes"] if h.hexdigest() == rec["sha256"] else None
+    return None
+
+
 def _timed(fn, steps, warmup, sync):
     for _ in range(warmup):
         fn()
@@ -159,7 +185,9 @@ def main():
     per_pair = 2 * d  # l2: one multiply-add per feature (2 flops); l1: subtract + abs-add
     tile_avg = tile_ms / max(tile_n, 1)
     roofline = roof(per_pair * cand, tile_avg)
-    roofline["traffic"] = None
+    roofline["traffic"] = (profiled_traffic("void rbc::tile_l2_mfma_items<4, 4>")
+                           if (metric, k) == ("l2", 1) else None)
+    roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)"
     roofline["kernel"] = "tile_l2_mfma_items (RBC stage 2)" if metric == "l2" else "tile_valu_items (RBC stage 2)"
     roofline["avg_ms"] = round(tile_avg, 4)
     roofline["algorithmic_units"] = "2*d*sum_q candidates = %d flops per launch" % (per_pair * cand)
@@ -271,8 +299,9 @@ def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32", "bf16")):
         res = {}
         # saturation: every request of a trace arrives at once
         t, sizes, ks, offs = datagen.arrival_trace("sub12", 1.0, n_requests, pool.shape[0])
+        ex = GpuExecutor(pool, search, ws_fn, 4, max_batch=4096, max_k=10)
+
         def run(times):
-            ex = GpuExecutor(pool, search, ws_fn, 4)
             sched = Scheduler(ex, 4, mem_budget=8 << 30, max_batch=4096)
             reqs = [Request(i, int(offs[i]), int(sizes[i]), int(ks[i]), float(times[i]))
                     for i in range(len(times))]

@@ -175,48 +175,74 @@ def latency_stats(reqs: List[Request]):
 class GpuExecutor:
     """Runs batches on torch streams with the library's search entry points.
 
-    ``search(Q, k, out, workspace)`` is called with the slot's stream current;
-    queries of a batch are gathered from the device-resident pool into one
-    contiguous block (a device copy on the same stream)."""
+    ``search(Q, k, out, workspace)`` is called with the slot's stream current.
+    Each slot owns, from construction on, a device arena sized for the largest
+    batch (``max_batch`` queries, any k <= ``max_k``): the search workspace,
+    a block the queries of a multi-request batch are gathered into, the
+    outputs, and pinned host buffers the outputs are copied back into on the
+    slot's stream.  Serving therefore calls no device allocator, and a batch
+    completes when its results are in host memory (the copy counts in the
+    latency).  ``results`` returns host tensors."""
 
-    def __init__(self, pool, search_fn, ws_fn, n_slots: int):
+    class _Slot:
+        pass
+
+    def __init__(self, pool, search_fn, ws_fn, n_slots: int, max_batch: int, max_k: int):
         import torch
 
         self.torch = torch
         self.pool = pool
         self.search_fn = search_fn
         self.ws_fn = ws_fn
-        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
-        self.live = {}
+        self.max_batch, self.max_k = max_batch, max_k
+        ws_max = max(int(ws_fn(max_batch, k)) for k in range(1, max_k + 1))
+        dev = pool.device
+        self.slots = []
+        for _ in range(n_slots):
+            sl = self._Slot()
+            sl.stream = torch.cuda.Stream()
+            sl.ws = torch.empty(max(1, ws_max), dtype=torch.uint8, device=dev)
+            sl.q = torch.empty((max_batch, pool.shape[1]), dtype=pool.dtype, device=dev)
+            sl.oi = torch.empty(max_batch * max_k, dtype=torch.int64, device=dev)
+            sl.od = torch.empty(max_batch * max_k, dtype=torch.float32, device=dev)
+            sl.hi = torch.empty(max_batch * max_k, dtype=torch.int64, pin_memory=True)
+            sl.hd = torch.empty(max_batch * max_k, dtype=torch.float32, pin_memory=True)
+            sl.ev = torch.cuda.Event()
+            self.slots.append(sl)
+        torch.cuda.synchronize()
 
     def workspace_bytes(self, m, k):
         return int(self.ws_fn(m, k))
 
     def launch(self, b: Batch):
         torch = self.torch
-        st = self.streams[b.slot]
-        st.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(st):
+        if b.m > self.max_batch or b.k > self.max_k:
+            raise ValueError("batch of %d queries, k=%d exceeds the slot arena (%d, %d)"
+                             % (b.m, b.k, self.max_batch, self.max_k))
+        sl = self.slots[b.slot]
+        sl.stream.wait_stream(torch.cuda.current_stream())
+        mk = b.m * b.k
+        with torch.cuda.stream(sl.stream):
             if len(b.parts) == 1:
                 req, s, cnt = b.parts[0]
                 Q = self.pool[req.offset + s:req.offset + s + cnt]
             else:
-                Q = torch.cat([self.pool[r.offset + s:r.offset + s + c] for (r, s, c) in b.parts])
-            ws = torch.empty(max(1, b.ws_bytes), dtype=torch.uint8, device=Q.device)
-            out = (torch.empty((b.m, b.k), dtype=torch.int64, device=Q.device),
-                   torch.empty((b.m, b.k), dtype=torch.float32, device=Q.device))
-            self.search_fn(Q, b.k, out, ws)
-            ev = torch.cuda.Event()
-            ev.record(st)
-        self.live[id(b)] = (Q, ws, out, ev)
-        return ev
+                Q = sl.q[:b.m]
+                torch.cat([self.pool[r.offset + s:r.offset + s + c] for (r, s, c) in b.parts], out=Q)
+            out = (sl.oi[:mk].view(b.m, b.k), sl.od[:mk].view(b.m, b.k))
+            self.search_fn(Q, b.k, out, sl.ws)
+            sl.hi[:mk].copy_(sl.oi[:mk], non_blocking=True)
+            sl.hd[:mk].copy_(sl.od[:mk], non_blocking=True)
+            sl.ev.record(sl.stream)
+        return sl.ev
 
     def done(self, ev):
         return ev.query()
 
     def results(self, b: Batch):
-        return self.live[id(b)][2]
+        sl = self.slots[b.slot]
+        mk = b.m * b.k
+        return (sl.hi[:mk].view(b.m, b.k).clone(), sl.hd[:mk].view(b.m, b.k).clone())
 
     def release(self, b: Batch):
-        # tensors return to the caching allocator on their stream
-        del self.live[id(b)]
+        pass

@@ -32,7 +32,7 @@ def test_served_results_equal_alone(orc):
     def ws_fn(m, k):
         return rbc.rbc_search_workspace_size(ix, m, k)
 
-    ex = GpuExecutor(Pd, search, ws_fn, 4)
+    ex = GpuExecutor(Pd, search, ws_fn, 4, max_batch=1024, max_k=10)
     sched = Scheduler(ex, 4, mem_budget=3 << 30, max_batch=1024)
     rng = np.random.default_rng(7)
     nreq = 250
