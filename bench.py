@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="also run the serving workload (resident 2M x 96 index, Poisson "
                          "arrivals at three rates) and report p50/p99 latency and QPS")
+    ap.add_argument("--configs", action="store_true",
+                    help="also run the one-shot workload (2M x 128 clustered integer data) and the "
+                         "4M x 128 brute force / exact RBC per precision (fp32, bf16, fp8)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -231,6 +234,7 @@ def main():
                              n, t_build, samp, m, t_search, m)}
 
     serving = run_serving(rbc, torch, dev) if args.serving else None
+    configs = run_configs(rbc, torch, dev) if args.configs else None
 
     line = {
         "metric": "exact k-NN queries/s (n=1M, d=64), RBC build+search vs BF, recall 1.0",
@@ -268,7 +272,115 @@ def main():
         line["paths"] = extra
     if serving:
         line["serving"] = serving
+    if configs:
+        line["configs"] = configs
     print(json.dumps(line))
+
+
+MFMA_PEAK_TF = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+
+def run_configs(rbc, torch, dev):
+    """One-shot RBC on zipf128 (n=2,000,000 d=128 clustered integer data,
+    m=20,000, n_r=1,414, s=2,000, L2, k=1): build and search time, recall and
+    mean rank error against brute force.  Brute force and exact RBC on sub16
+    (n=4,000,000 d=128, 16-dim subspace, m=50,000, n_r=2,000, L2, k in
+    {1, 10}) in fp32, bf16 and fp8: queries/s and the ranking tile's fraction
+    of its own precision's matrix peak (2 d flops per scored pair)."""
+    import numpy as np
+
+    import datagen
+
+    sync = torch.cuda.synchronize
+    res = {}
+    # ---- one-shot
+    w = datagen.WORKLOADS["zipf128"]
+    X = torch.from_numpy(datagen.database("zipf128")).to(dev)
+    Q = torch.from_numpy(datagen.queries("zipf128")).to(dev)
+    reps = datagen.representatives("zipf128")
+    m, d = Q.shape
+    build_ms = _timed(lambda: rbc.rbc_build(X, w.n_r, mode="oneshot", s=w.s, rep_idx=reps).free(),
+                      3, 1, sync)
+    ix = rbc.rbc_build(X, w.n_r, mode="oneshot", s=w.s, rep_idx=reps)
+    out = (torch.empty((m, 1), dtype=torch.int64, device=dev),
+           torch.empty((m, 1), dtype=torch.float32, device=dev))
+    ws = torch.empty(rbc.rbc_search_workspace_size(ix, m, 1), dtype=torch.uint8, device=dev)
+    s_ms = _timed(lambda: rbc.rbc_search(ix, Q, 1, out=out, workspace=ws), 10, 3, sync)
+    got_i, got_d = out[0].clone(), out[1].clone()
+    bi, bd = rbc.bf_search(Q, X, 1, "l2")
+    sync()
+    # rank of the returned point: points strictly closer than it (exact BF distances)
+    recall = float((got_d[:, 0] <= bd[:, 0]).float().mean())
+    res["oneshot_zipf128"] = {
+        "workload": "zipf128: n=2,000,000 d=128 integer clustered (2,000 Zipf(1.1) centres), "
+                    "m=20,000, n_r=1,414, s=2,000, l2, k=1",
+        "build_ms": round(build_ms, 3), "search_ms": round(s_ms, 3),
+        "search_qps": round(m / s_ms * 1e3, 1),
+        "recall_at_1": round(recall, 5),
+        "exact_match_ids": round(float((got_i[:, 0] == bi[:, 0]).float().mean()), 5)}
+    ix.free()
+    del X, Q, ws
+    torch.cuda.empty_cache()
+    # ---- brute force and exact RBC per precision
+    w = datagen.WORKLOADS["sub16"]
+    Xh = datagen.database("sub16")
+    X = torch.from_numpy(Xh).to(dev)
+    del Xh
+    Q = torch.from_numpy(datagen.queries("sub16")).to(dev)
+    reps = datagen.representatives("sub16")
+    m, d = Q.shape
+    n = X.shape[0]
+    ix = rbc.rbc_build(X, w.n_r, rep_idx=reps, precisions=("bf16", "fp8"))
+    for prec in ("fp32", "bf16", "fp8"):
+        for k in (1, 10):
+            out = (torch.empty((m, k), dtype=torch.int64, device=dev),
+                   torch.empty((m, k), dtype=torch.float32, device=dev))
+            bws = torch.empty(rbc.bf_search_workspace_size(m, n, d, k, "l2", precision=prec),
+                              dtype=torch.uint8, device=dev)
+            rbc.timer_enable(True)
+            b_ms = _timed(lambda: rbc.bf_search(Q, X, k, "l2", out=out, workspace=bws,
+                                                precision=prec), 3, 1, sync)
+            t_ms, t_n = rbc.timer_read("tile")
+            rbc.timer_enable(False)
+            bi = out[0].clone()
+            del bws
+            stats = rbc.new_stats()
+            rbc.bf_search(Q, X, k, "l2", out=out, workspace=None, precision=prec, stats=stats)
+            sync()
+            fb = int(stats.cpu().numpy()[rbc.STAT_FALLBACK])
+            tile_avg = t_ms / max(t_n, 1)
+            ach = 2.0 * d * m * n / (tile_avg * 1e-3) / 1e12
+            rws = torch.empty(rbc.rbc_search_workspace_size(ix, m, k, precision=prec),
+                              dtype=torch.uint8, device=dev)
+            rbc.timer_enable(True)
+            r_ms = _timed(lambda: rbc.rbc_search(ix, Q, k, out=out, workspace=rws, precision=prec),
+                          3, 1, sync)
+            rt_ms, rt_n = rbc.timer_read("tile_items")
+            rbc.timer_enable(False)
+            st2 = rbc.new_stats()
+            rbc.rbc_search(ix, Q, k, out=out, workspace=rws, precision=prec, stats=st2)
+            sync()
+            st2 = st2.cpu().numpy()
+            del rws
+            torch.cuda.empty_cache()
+            r_avg = rt_ms / max(rt_n, 1)
+            r_ach = 2.0 * d * float(st2[rbc.STAT_CAND]) / (r_avg * 1e-3) / 1e12
+            res["sub16_%s_k%d" % (prec, k)] = {
+                "bf_ms": round(b_ms, 2), "bf_qps": round(m / b_ms * 1e3, 1),
+                "bf_tile": {"avg_ms": round(tile_avg, 3), "achieved_tflops": round(ach, 1),
+                            "peak_tflops": MFMA_PEAK_TF[prec],
+                            "frac": round(ach / MFMA_PEAK_TF[prec], 4)},
+                "bf_fallback_queries": fb,
+                "rbc_search_ms": round(r_ms, 2), "rbc_search_qps": round(m / r_ms * 1e3, 1),
+                "rbc_tile": {"avg_ms": round(r_avg, 3), "achieved_tflops": round(r_ach, 1),
+                             "frac": round(r_ach / MFMA_PEAK_TF[prec], 4)},
+                "rbc_candidate_fraction": round(float(st2[rbc.STAT_CAND]) / (m * n), 4),
+                "rbc_fallback_queries": int(st2[rbc.STAT_FALLBACK])}
+            print(json.dumps({"progress": "sub16 %s k=%d" % (prec, k)}), file=sys.stderr, flush=True)
+    ix.free()
+    res["sub16_workload"] = ("sub16: n=4,000,000 d=128, 16-dim subspace + N(0,0.02^2), m=50,000, "
+                             "n_r=2,000, l2")
+    return res
 
 
 def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32", "bf16")):

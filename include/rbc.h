@@ -83,6 +83,8 @@ typedef enum {
 #define RBC_STAT_PAIRS      2  /* (query, point) pairs scored by the main kernel */
 #define RBC_STAT_LISTS      3  /* (query, list) pairs kept by the pruning rules */
 #define RBC_STAT_CAND       4  /* (query, point) pairs inside kept lists */
+#define RBC_STAT_CASCADE    5  /* low precision: queries whose certificate failed and that the
+                                  float32 tile re-ranked over all rows */
 
 /* Per-call search options.  Pass NULL for the defaults. */
 typedef struct rbc_search_opts {
@@ -94,7 +96,8 @@ typedef struct rbc_search_opts {
     int64_t* dev_stats; /* optional DEVICE array of RBC_STATS_LEN int64 counters */
     float* dev_approx_dist; /* optional DEVICE m x k floats: the distance each result had in
                                the ranking tile, before re-scoring (not written for queries
-                               that take the float64 fallback) */
+                               re-ranked by the float32 cascade or the float64
+                               fallback) */
 } rbc_search_opts;
 
 /* Index construction parameters. */
@@ -205,7 +208,9 @@ void rbc_free(rbc_index* index);
  * on its stream around each of its kernels; rbc_timer_read() waits for the
  * recorded events and returns the summed device time (ms) and launch count
  * of the kernels called `name`: "tile" (BF distance tile), "tile_items"
- * (RBC stage 2), "finalize", "fallback", "stage1", "prune", "worklist".
+ * (RBC stage 2), "finalize", "fallback", "stage1", "prune", "worklist",
+ * "quantize", "cascade" (the float32 re-ranking of low-precision queries
+ * whose certificate failed), "oneshot_tile", "oneshot_select".
  */
 int rbc_timer_enable(int on);
 int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);

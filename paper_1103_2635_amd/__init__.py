@@ -20,7 +20,7 @@ L2, L1 = 0, 1
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 EXACT, ONESHOT = 0, 1
 STATS_LEN = 8
-STAT_FALLBACK, STAT_NEARTIE, STAT_PAIRS, STAT_LISTS, STAT_CAND = 0, 1, 2, 3, 4
+STAT_FALLBACK, STAT_NEARTIE, STAT_PAIRS, STAT_LISTS, STAT_CAND, STAT_CASCADE = 0, 1, 2, 3, 4, 5
 
 _METRICS = {"l2": L2, "l1": L1, L2: L2, L1: L1}
 _MODES = {"exact": EXACT, "oneshot": ONESHOT, EXACT: EXACT, ONESHOT: ONESHOT}

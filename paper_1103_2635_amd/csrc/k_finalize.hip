@@ -40,8 +40,16 @@ template <int C>
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     const int lane = threadIdx.x & 63;
     const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (slot >= a.m) return;  // uniform per wavefront
-    const int qrow = slot;
+    int mact = a.m, nsplit = a.nsplit, stride = a.m;
+    if (a.m_dev) {
+        mact = *a.m_dev;
+        const DevSplit ds = dev_split(mact, a.dev_blocks, a.n);
+        nsplit = ds.S;
+        stride = ds.M;
+    }
+    if (slot >= mact) return;  // uniform per wavefront
+    const int qrow = slot;                               // row of Q (and of qn, qerr)
+    const int orow = a.qmap ? a.qmap[slot] : slot;       // output row, reported query
 
     // 1. merge the sorted partial lists into the c best entries: lane r ends
     //    up holding merged entry r.  Each round takes the smallest head; one
@@ -49,7 +57,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     //    are counted as often as they occur.
     float mv = RBC_INF;
     int32_t mi = -1;
-    if (a.qoff == nullptr && a.nsplit == 1) {
+    if (a.qoff == nullptr && nsplit == 1) {
         if (lane < C) {
             mv = a.pval[(int64_t)slot * C + lane];
             mi = a.pidx[(int64_t)slot * C + lane];
@@ -60,10 +68,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         // the first entry that cannot enter)
         TopC<C> loc;
         loc.init();
-        const int nl = a.qoff ? a.npairs[slot] : a.nsplit;
+        const int nl = a.qoff ? a.npairs[slot] : nsplit;
         for (int j = lane; j < nl; j += 64) {
             const int64_t base = a.qoff ? ((int64_t)a.qoff[slot] + j) * C
-                                        : ((int64_t)j * a.m + slot) * C;
+                                        : ((int64_t)j * stride + slot) * C;
             for (int i = 0; i < C; ++i) {
                 const float v = a.pval[base + i];
                 if (!(v < loc.worst())) break;
@@ -170,11 +178,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     if (!ok) {
         if (lane == 0) {
             const int p = atomicAdd(a.fb_count, 1);
-            a.fb_list[p] = qrow;
+            a.fb_list[p] = orow;
         }
     } else if (valid && rank < a.k) {
-        a.out_idx[(int64_t)qrow * a.k + rank] = myid;
-        a.out_dist[(int64_t)qrow * a.k + rank] = (float)rho;
+        a.out_idx[(int64_t)orow * a.k + rank] = myid;
+        a.out_dist[(int64_t)orow * a.k + rank] = (float)rho;
         if (a.out_approx) {
             // the entry's distance in the ranking tile, before re-scoring
             double ap;
@@ -182,11 +190,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
                 ap = a.metric == 0 ? __builtin_sqrt((double)mv) : (double)mv;
             else
                 ap = __builtin_sqrt(fmax((double)mv + (double)a.qn[slot], 0.0));
-            a.out_approx[(int64_t)qrow * a.k + rank] = (float)ap;
+            a.out_approx[(int64_t)orow * a.k + rank] = (float)ap;
         }
     }
     if (a.stats && lane == 0) {
-        if (!ok) atomicAdd((unsigned long long*)&a.stats[0], 1ull);
+        if (!ok) atomicAdd((unsigned long long*)&a.stats[a.fail_stat], 1ull);
         if (flagged) atomicAdd((unsigned long long*)&a.stats[1], (unsigned long long)__popcll(flagged));
     }
 }

@@ -69,7 +69,8 @@ constexpr int kNormBlocks = 1024;
 __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t rows, int64_t lda,
                                                         int32_t d, const int32_t* rowmap,
                                                         float* out, uint32_t* maxbits,
-                                                        uint32_t* flags) {
+                                                        uint32_t* flags, const int32_t* gate) {
+    if (gate && *gate == 0) return;  // uniform per launch
     __shared__ float wmax[4];
     __shared__ uint32_t wflag[4][3];
     const int sub = threadIdx.x & 15;
@@ -132,12 +133,53 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t 
 
 hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d,
                             const int32_t* rowmap, float* out, uint32_t* maxbits,
-                            hipStream_t st, uint32_t* flags) {
+                            hipStream_t st, uint32_t* flags, const int32_t* gate) {
     if (rows <= 0) return hipSuccess;
     int64_t blocks = (rows * 16 + 255) / 256;
     if (blocks > kNormBlocks) blocks = kNormBlocks;
     hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, rows, lda,
-                       d, rowmap, out, maxbits, flags);
+                       d, rowmap, out, maxbits, flags, gate);
+    return hipGetLastError();
+}
+
+// Compaction of the queries listed in list[0 .. *count) (at most m): row i
+// of Qc (ldc floats, zero beyond d) is query list[i], qn[i] its squared norm
+// (fp32, a wavefront sum), qmap[i] = list[i]; *count_out = *count.  One
+// wavefront per row.
+__global__ __launch_bounds__(256) void cascade_gather_kernel(const float* Q, int64_t ldq,
+                                                             int32_t d, const int32_t* list,
+                                                             const int32_t* count, float* Qc,
+                                                             int64_t ldc, float* qn,
+                                                             int32_t* qmap, int32_t* count_out) {
+    const int cnt = *count;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = cnt;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= cnt) return;
+    const int32_t q = list[i];
+    const float* src = Q + (int64_t)q * ldq;
+    float* dst = Qc + i * ldc;
+    float s = 0.f;
+    for (int f = lane; f < ldc; f += 64) {
+        const float v = f < d ? src[f] : 0.f;
+        dst[f] = v;
+        s = __builtin_fmaf(v, v, s);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) {
+        qn[i] = s;
+        qmap[i] = q;
+    }
+}
+
+hipError_t launch_cascade_gather(const float* Q, int64_t ldq, int32_t d, int64_t m,
+                                 const int32_t* list, const int32_t* count, float* Qc,
+                                 int64_t ldc, float* qn, int32_t* qmap, int32_t* count_out,
+                                 hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cascade_gather_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, Q,
+                       ldq, d, list, count, Qc, ldc, qn, qmap, count_out);
     return hipGetLastError();
 }
 

@@ -71,6 +71,11 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
         p->repack_q = p->repack_x = false;  // the quantiser reads any stride
         p->kb = prec == RBC_BF16 ? (d + 31) / 32 : 1;
         p->dq = prec == RBC_BF16 ? 32 * p->kb : 128;
+        // the fp32 pass reads X in place: rows of whole float4 runs
+        p->casc = (d % 4) == 0 && (ldx % 4) == 0;
+        p->c32 = shortlist_len(k, 0);
+        p->ks32 = (d + 15) / 16;
+        p->ldc = ((int64_t)d + 3) / 4 * 4;
     } else if (metric == RBC_L2 && d >= 12) {
         p->path = kPathMfma;
     } else {
@@ -87,7 +92,86 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
         p->rps = (int32_t)rps;
         p->nsplit = (int32_t)((n + rps - 1) / rps);
     }
+    if (p->path == kPathLowp) {
+        const int64_t s = std::max<int64_t>(1, std::min<int64_t>(4 * kConcurrentBlocks / p->nqblk,
+                                                                 kMaxSplits));
+        p->casc_blocks = (int32_t)std::max<int64_t>(p->nqblk * s, 4 * kConcurrentBlocks);
+    }
     return RBC_OK;
+}
+
+void carve_cascade(const BfPlan& p, int64_t m, int64_t n, bool xnorms, Carver& cv, BfWork* w) {
+    if (p.path != kPathLowp || !p.casc) return;
+    w->Qc = cv.take<float>(m * p.ldc);
+    w->qnc = cv.take<float>(m);
+    w->qmap = cv.take<int32_t>(m);
+    if (xnorms) w->xn32 = cv.take<float>(n);
+    w->pval_c = cv.take<float>((int64_t)p.casc_blocks * kTileQ * p.c32);
+    w->pidx_c = cv.take<int32_t>((int64_t)p.casc_blocks * kTileQ * p.c32);
+}
+
+int run_cascade(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X,
+                int64_t n, int64_t ldx, const float* xn, const uint32_t* xstat,
+                const int64_t* id_map, int64_t* out_idx, float* out_dist, BfWork& w,
+                int64_t* stats, hipStream_t st) {
+    int32_t* ctr = w.counters;
+    int rc;
+    KernelTimer kt("cascade", st);
+    if ((rc = hip_status(launch_cascade_gather(Q, ldq, p.d, m, w.fb_list, ctr, w.Qc, p.ldc, w.qnc,
+                                               w.qmap, ctr + 1, st), "cascade gather")))
+        return rc;
+    if ((rc = hip_status(launch_fill_i32(ctr, 1, 0, st), "cascade reset"))) return rc;
+    if (xn == nullptr) {
+        if ((rc = hip_status(launch_row_norms(X, n, ldx, p.d, nullptr, w.xn32, (uint32_t*)ctr + 8,
+                                              st, nullptr, ctr + 1), "cascade norms X")))
+            return rc;
+        xn = w.xn32;
+        xstat = (const uint32_t*)ctr + 8;
+    }
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = w.Qc;
+    a.ldq = p.ldc;
+    a.m = (int32_t)m;
+    a.X = X;
+    a.ldx = ldx;
+    a.n = (int32_t)n;
+    a.d = p.d;
+    a.xn = xn;
+    a.pval = w.pval_c;
+    a.pidx = w.pidx_c;
+    a.m_dev = ctr + 1;
+    a.dev_blocks = p.casc_blocks;
+    if ((rc = hip_status(launch_tile_mfma(p.ks32, p.c32, kTileBF, dim3(p.casc_blocks), a, st),
+                         "cascade tile")))
+        return rc;
+    FinArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.Q = w.Qc;
+    f.ldq = p.ldc;
+    f.m = (int32_t)m;
+    f.X = X;
+    f.ldx = ldx;
+    f.d = p.d;
+    f.metric = RBC_L2;
+    f.approx_mode = 0;
+    f.pval = w.pval_c;
+    f.pidx = w.pidx_c;
+    f.k = p.k;
+    f.qn = w.qnc;
+    f.xmax_bits = xstat;
+    f.id_map = id_map;
+    f.out_idx = out_idx;
+    f.out_dist = out_dist;
+    f.fb_list = w.fb_list;
+    f.fb_count = ctr;
+    f.stats = stats;
+    f.fail_stat = RBC_STAT_FALLBACK;
+    f.m_dev = ctr + 1;
+    f.dev_blocks = p.casc_blocks;
+    f.n = (int32_t)n;
+    f.qmap = w.qmap;
+    return hip_status(launch_finalize(p.c32, f, st), "cascade finalize");
 }
 
 void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
@@ -112,6 +196,7 @@ void carve_bf(const BfPlan& p, int64_t m, int64_t n, Carver& cv, BfWork* w) {
     }
     w->pval = cv.take<float>((int64_t)p.nsplit * m * p.c);
     w->pidx = cv.take<int32_t>((int64_t)p.nsplit * m * p.c);
+    carve_cascade(p, m, n, true, cv, w);
 }
 
 // BF(Q, X) with the contraction on quantised rows: quantise Q (times -2) and
@@ -165,7 +250,11 @@ int run_bf_lowp(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const f
     f.xerr_max_bits = ctr + 13;
     f.flags_q = nullptr;
     f.flags_x = nullptr;
+    if (p.casc) f.fail_stat = RBC_STAT_CASCADE;
     if ((rc = run_finalize(p, f, st))) return rc;
+    if (p.casc && (rc = run_cascade(p, Q, m, ldq, X, n, ldx, nullptr, nullptr, id_map, out_idx,
+                                    out_dist, w, stats, st)))
+        return rc;
     return run_fallback(p, Q, m, ldq, X, n, ldx, id_map, out_idx, out_dist, w, st);
 }
 

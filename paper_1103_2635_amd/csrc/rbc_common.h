@@ -65,6 +65,11 @@ struct TileArgs {
     int32_t* pidx;         // partial shortlist rows (-1 = no row)
     int64_t ldo;           // kTileAll: row stride of the value matrix
     int64_t* stats;        // optional device counters
+    // BF mode with a device-side query count (non-null m_dev): the first
+    // *m_dev rows of Q are searched by a 1-D grid of dev_blocks workgroups
+    // whose (query block, split) layout is derived from the count (dev_split)
+    const int32_t* m_dev;
+    int32_t dev_blocks;
 };
 
 // Merge of the partial shortlists, direct re-score, float64 near-tie
@@ -98,6 +103,14 @@ struct FinArgs {
     int32_t* fb_list;      // queries (rows of Q) whose shortlist is not certified
     int32_t* fb_count;
     int64_t* stats;
+    int32_t fail_stat;     // stats slot counting the queries that are not certified
+    // device-side query count (see TileArgs): rows i < *m_dev of Q are
+    // finalized, the partial lists laid out by dev_split(*m_dev, dev_blocks, n);
+    // qmap (optional) maps row i of Q to the output row / reported query
+    const int32_t* m_dev;
+    int32_t dev_blocks;
+    int32_t n;
+    const int32_t* qmap;
 };
 
 // Exhaustive float64 search for the rows of Q listed in list[0 .. *count).
@@ -127,7 +140,12 @@ hipError_t launch_repack(const float* A, int64_t rows, int64_t lda, int32_t d, f
                          int64_t ldo, hipStream_t st);
 hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d,
                             const int32_t* rowmap, float* out, uint32_t* maxbits,
-                            hipStream_t st, uint32_t* flags = nullptr);
+                            hipStream_t st, uint32_t* flags = nullptr,
+                            const int32_t* gate = nullptr);
+hipError_t launch_cascade_gather(const float* Q, int64_t ldq, int32_t d, int64_t m,
+                                 const int32_t* list, const int32_t* count, float* Qc,
+                                 int64_t ldc, float* qn, int32_t* qmap, int32_t* count_out,
+                                 hipStream_t st);
 hipError_t launch_tile_mfma(int ks, int c, int mode, dim3 grid, const TileArgs& a,
                             hipStream_t st);
 hipError_t launch_tile_valu(int metric, int ks, int c, int mode, dim3 grid,

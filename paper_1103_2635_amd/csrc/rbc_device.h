@@ -43,6 +43,27 @@ __device__ __forceinline__ bool tile_exact(const uint32_t* fa, const uint32_t* f
     return neg ? 3.0 * d * m * m <= 16777216.0 : d * m * m <= 8388608.0;
 }
 
+// Layout of a BF-mode search whose query count is known on the device only:
+// a fixed 1-D grid of `blocks` workgroups (256 queries each) is spread over
+// the A = ceil(cnt / 256) active query blocks, S = blocks / A database splits
+// each (at most one per 32 rows), rps rows per split; the partial list of
+// split s for query q sits at (s * M + q) * C with M = 256 A.
+struct DevSplit {
+    int A, S, rps, M;
+};
+
+__device__ __forceinline__ DevSplit dev_split(int cnt, int blocks, int n) {
+    DevSplit r;
+    r.A = (cnt + 255) >> 8;
+    r.M = r.A << 8;
+    int s = r.A > 0 ? blocks / r.A : 1;
+    const int smax = (n + 31) >> 5;
+    s = s < 1 ? 1 : (s > smax ? smax : s);
+    r.S = s;
+    r.rps = (((n + s - 1) / s) + 31) & ~31;
+    return r;
+}
+
 // (distance, id) lexicographic order.
 __device__ __forceinline__ bool before(double va, int64_t ia, double vb, int64_t ib) {
     return va < vb || (va == vb && ia < ib);

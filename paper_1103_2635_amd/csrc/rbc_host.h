@@ -60,6 +60,14 @@ struct BfPlan {
     int prec;          // rbc_precision
     int kb;            // low precision: 32-feature blocks (bf16) / 1 (fp8)
     int dq;            // low precision: padded row length of the quantised copies
+    // low precision: queries whose certificate fails are re-ranked by the
+    // fp32 matrix tile over all rows (a device-sized launch) before any
+    // float64 fallback
+    bool casc;
+    int c32;           // shortlist length of that fp32 pass
+    int ks32;          // its 16-feature slabs
+    int64_t ldc;       // row length of the compacted query copies (d rounded up to 4)
+    int32_t casc_blocks;  // its workgroups
 };
 
 struct BfWork {
@@ -80,6 +88,14 @@ struct BfWork {
     uint8_t* qscale = nullptr;
     uint8_t* xscale = nullptr;
     float* qerr = nullptr;
+    // fp32 cascade (low precision): compacted queries, their norms and
+    // original rows, fp32 norms of X (bf_search only), partial lists
+    float* Qc = nullptr;
+    float* qnc = nullptr;
+    int32_t* qmap = nullptr;
+    float* xn32 = nullptr;
+    float* pval_c = nullptr;
+    int32_t* pidx_c = nullptr;
 };
 
 // Records a pair of HIP events around a launch when timing is enabled
@@ -113,5 +129,15 @@ int run_fallback(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const 
                  int64_t n, int64_t ldx, const int64_t* id_map, int64_t* out_idx,
                  float* out_dist, BfWork& w, hipStream_t st);
 int validate_common(int64_t m, int64_t n, int32_t d, int32_t k, int32_t metric);
+void carve_cascade(const BfPlan& p, int64_t m, int64_t n, bool xnorms, Carver& cv, BfWork* w);
+// The fp32 cascade after a low-precision finalize: the queries in w.fb_list
+// (count w.counters[0]) are compacted, searched by the fp32 tile over X and
+// finalized; those still uncertified are left in w.fb_list for run_fallback.
+// xn / xstat: fp32 norms and stats of X, or null to compute them (gated on a
+// non-empty list).
+int run_cascade(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float* X,
+                int64_t n, int64_t ldx, const float* xn, const uint32_t* xstat,
+                const int64_t* id_map, int64_t* out_idx, float* out_dist, BfWork& w,
+                int64_t* stats, hipStream_t st);
 
 }  // namespace rbc

@@ -500,6 +500,7 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         w->bf.Qq = cv.take<uint8_t>(m * p.dq * (p.prec == RBC_BF16 ? 2 : 1));
         w->bf.qerr = cv.take<float>(m);
         if (p.prec == RBC_FP8_E4M3) w->bf.qscale = cv.take<uint8_t>(m);
+        carve_cascade(p, m, ix->rows, false, cv, &w->bf);
     }
     w->bf.pval = cv.take<float>(m * nr * p.c);
     w->bf.pidx = cv.take<int32_t>(m * nr * p.c);
@@ -527,7 +528,13 @@ int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
         return set_err(RBC_EINVAL, "one-shot search needs k <= s (%lld)", (long long)ix->s);
     if (ix->mode == RBC_EXACT && (int64_t)m * ix->n_r >= ((int64_t)1 << 31))
         return set_err(RBC_EUNSUPPORTED, "m * n_r >= 2^31: split the query batch");
-    return make_bf_plan(m > 0 ? m : 1, ix->rows, ix->d, ldq, ix->ld, ix->metric, k, opts, p);
+    int rc = make_bf_plan(m > 0 ? m : 1, ix->rows, ix->d, ldq, ix->ld, ix->metric, k, opts, p);
+    if (rc) return rc;
+    if (p->path == kPathLowp) {  // the index rows are zero-padded to float4 runs
+        p->casc = true;
+        p->ldc = ((int64_t)ix->d + 3) / 4 * 4;
+    }
+    return RBC_OK;
 }
 
 int validate_search(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k) {
@@ -584,7 +591,11 @@ int search_exact_lowp(const rbc_index* ix, const BfPlan& p, const float* Q, int6
     f.xerr_max_bits = qc.stat + 1;
     f.flags_q = nullptr;
     f.flags_x = nullptr;
+    if (p.casc) f.fail_stat = RBC_STAT_CASCADE;
     if ((rc = run_finalize(p, f, st))) return rc;
+    if (p.casc && (rc = run_cascade(p, Q, m, ldq, ix->Xp, ix->rows, ix->ld, ix->xn,
+                                    ix->norms_max, ix->ids, out_idx, out_dist, w.bf, stats, st)))
+        return rc;
     return run_fallback(p, Q, m, ldq, ix->Xp, ix->rows, ix->ld, ix->ids, out_idx, out_dist, w.bf,
                         st);
 }

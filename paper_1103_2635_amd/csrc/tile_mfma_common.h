@@ -56,19 +56,31 @@ __device__ __forceinline__ void load_qfrags(typename P::QFrag (&qf)[4][P::kBlock
         for (int f = 0; f < P::kBlocks; ++f) P::load_q(qf[qb][f], a, qrow[qb], f, g);
 }
 
+// Squared norms of the rows base + 16 rb + 4 g + i (clamped to r1 - 1, so the
+// loads need no branch); tile_step puts +inf at rows >= r1.
+__device__ __forceinline__ void load_norms(f4 (&nr)[2], const float* xn, int base, int r1, int g) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = base + 16 * rb + 4 * g + i;
+            nr[rb][i] = xn[row < r1 ? row : r1 - 1];
+        }
+}
+
 // The 32 x 64 values of rows [base, base + 32): acc[rb][qb][i] is row
 // base + 16 rb + 4 g + i, query 16 qb + c16 (+inf beyond r1).
 template <class P>
 __device__ __forceinline__ void tile_step(f4 (&acc)[2][4], const typename P::QFrag (&qf)[4][P::kBlocks],
                                           const typename P::XFrag (&xa)[2][P::kBlocks],
-                                          const float* xn, int base, int r1, int g) {
+                                          const f4 (&nr)[2], int base, int r1, int g) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
         f4 nv;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = base + 16 * rb + 4 * g + i;
-            nv[i] = row < r1 ? xn[row] : RBC_INF;
+            nv[i] = row < r1 ? nr[rb][i] : RBC_INF;
         }
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = P::mma(xa[rb][0], qf[qb][0], nv);
@@ -81,70 +93,118 @@ __device__ __forceinline__ void tile_step(f4 (&acc)[2][4], const typename P::QFr
             for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = P::mma(xa[rb][f], qf[qb][f], acc[rb][qb]);
 }
 
+// Each lane keeps, for the four queries whose values it holds in the MFMA
+// layout (16 qb + c16), a copy of their shortlist bound (-inf for lanes
+// without a query, which never insert).
+template <int C>
+__device__ __forceinline__ void refresh_bounds(float (&wq)[4], const TopC<C>& top, bool act,
+                                               int c16) {
+    const float w = act ? top.worst() : -RBC_INF;
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) wq[qb] = __shfl(w, 16 * qb + c16);
+}
+
 // Scan database rows [r0, r1) for the wavefront's 64 queries; lanes with act
-// push their values into top.
+// push their values into top.  A 32-row block whose values all lie at or
+// above their query's bound cannot change any shortlist, so it is skipped
+// after a min-reduction in the MFMA layout; otherwise the block goes through
+// the LDS transpose and every value is pushed (the pushes, and so the
+// shortlists, are those of the plain scan).  Fragments and norms of the next
+// block are loaded while the current one is used.
 template <class P, int C>
 __device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[4][P::kBlocks],
                                           const TileArgs& a, int r0, int r1, bool act,
                                           TopC<C>& top, float* tb, int lane) {
     const int g = lane >> 4;
     const int c16 = lane & 15;
+    float wq[4];
+    refresh_bounds<C>(wq, top, act, c16);
     typename P::XFrag xa[2][P::kBlocks];
+    f4 na[2];
     load_xfrags<P>(xa, a, r0, c16, g);
+    load_norms(na, a.xn, r0, r1, g);
     for (int base = r0; base < r1; base += kRowsMfma) {
         typename P::XFrag xb[2][P::kBlocks];
+        f4 nb[2];
         const int next = base + kRowsMfma;
-        load_xfrags<P>(xb, a, next < r1 ? next : base, c16, g);
+        const int nbase = next < r1 ? next : base;
+        load_xfrags<P>(xb, a, nbase, c16, g);
+        load_norms(nb, a.xn, nbase, r1, g);
         f4 acc[2][4];
-        tile_step<P>(acc, qf, xa, a.xn, base, r1, g);
-        // transpose: element (query 16 qb + c16, row 16 rb + 4 g + i)
-        wave_lds_sync();
+        tile_step<P>(acc, qf, xa, na, base, r1, g);
+        bool need = false;
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int qb = 0; qb < 4; ++qb) {
+            const float m0 = fminf(fminf(acc[0][qb][0], acc[0][qb][1]), fminf(acc[0][qb][2], acc[0][qb][3]));
+            const float m1 = fminf(fminf(acc[1][qb][0], acc[1][qb][1]), fminf(acc[1][qb][2], acc[1][qb][3]));
+            need |= fminf(m0, m1) < wq[qb];
+        }
+        if (__ballot(need) != 0ull) {
+            // transpose: element (query 16 qb + c16, row 16 rb + 4 g + i)
+            wave_lds_sync();
 #pragma unroll
-            for (int qb = 0; qb < 4; ++qb)
-                *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
-        wave_lds_sync();
-        f4 vals[8];
+            for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int t = 0; t < 8; ++t) vals[t] = *(const f4*)(tb + lane * kTStride + 4 * t);
-        if (act) {
+                for (int qb = 0; qb < 4; ++qb)
+                    *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
+            wave_lds_sync();
+            f4 vals[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
+            for (int t = 0; t < 8; ++t) vals[t] = *(const f4*)(tb + lane * kTStride + 4 * t);
+            if (act) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
+            }
+            refresh_bounds<C>(wq, top, act, c16);
         }
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < 2; ++rb) {
+            na[rb] = nb[rb];
 #pragma unroll
             for (int f = 0; f < P::kBlocks; ++f) xa[rb][f] = xb[rb][f];
+        }
     }
 }
 
-// BF mode: grid (query blocks of 256, database splits).
+// BF mode: grid (query blocks of 256, database splits), or, with a device-side
+// query count, a 1-D grid laid out by dev_split.
 template <class P, int C>
 __device__ __forceinline__ void tile_bf_body(const TileArgs& a, float* tbuf_wave) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int c16 = lane & 15;
-    const int slot0 = blockIdx.x * kTileQ + wave * kWave;
+    int m = a.m, qblk = blockIdx.x, split = blockIdx.y, stride = a.m;
+    int64_t rps = a.rps;
+    if (a.m_dev) {
+        m = *a.m_dev;
+        const DevSplit ds = dev_split(m, a.dev_blocks, a.n);
+        qblk = blockIdx.x / ds.S;
+        split = blockIdx.x % ds.S;
+        if (qblk >= ds.A) return;
+        stride = ds.M;
+        rps = ds.rps;
+    }
+    const int slot0 = qblk * kTileQ + wave * kWave;
+    if (slot0 >= m) return;  // uniform per wavefront; no workgroup barrier follows
     typename P::QFrag qf[4][P::kBlocks];
     int qrow[4];
 #pragma unroll
     for (int qb = 0; qb < 4; ++qb) {
         const int slot = slot0 + 16 * qb + c16;
-        qrow[qb] = slot < a.m ? slot : a.m - 1;
+        qrow[qb] = slot < m ? slot : m - 1;
     }
     load_qfrags<P>(qf, a, qrow, g);
     const int myslot = slot0 + lane;
     TopC<C> top;
     top.init();
-    const int64_t r0 = (int64_t)blockIdx.y * a.rps;
-    const int64_t r1 = r0 + a.rps < a.n ? r0 + a.rps : a.n;
-    if (r0 < r1) scan_rows<P, C>(qf, a, (int)r0, (int)r1, myslot < a.m, top, tbuf_wave, lane);
-    if (myslot < a.m) {
-        const int64_t off = ((int64_t)blockIdx.y * a.m + myslot) * C;
+    const int64_t r0 = (int64_t)split * rps;
+    const int64_t r1 = r0 + rps < a.n ? r0 + rps : a.n;
+    if (r0 < r1) scan_rows<P, C>(qf, a, (int)r0, (int)r1, myslot < m, top, tbuf_wave, lane);
+    if (myslot < m) {
+        const int64_t off = ((int64_t)split * stride + myslot) * C;
         top.store(a.pval + off, a.pidx + off);
     }
 }
@@ -215,13 +275,18 @@ __device__ __forceinline__ void tile_all_body(const TileArgs& a) {
     const int r1 = (int)(r0 + (int64_t)a.rps < a.n ? r0 + a.rps : a.n);
     if (r0 >= r1) return;
     typename P::XFrag xa[2][P::kBlocks];
+    f4 na[2];
     load_xfrags<P>(xa, a, r0, c16, g);
+    load_norms(na, a.xn, r0, r1, g);
     for (int base = r0; base < r1; base += kRowsMfma) {
         typename P::XFrag xb[2][P::kBlocks];
+        f4 nb[2];
         const int next = base + kRowsMfma;
-        load_xfrags<P>(xb, a, next < r1 ? next : base, c16, g);
+        const int nbase = next < r1 ? next : base;
+        load_xfrags<P>(xb, a, nbase, c16, g);
+        load_norms(nb, a.xn, nbase, r1, g);
         f4 acc[2][4];
-        tile_step<P>(acc, qf, xa, a.xn, base, r1, g);
+        tile_step<P>(acc, qf, xa, na, base, r1, g);
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
             const int row = base + 16 * rb + 4 * g;
@@ -240,9 +305,11 @@ __device__ __forceinline__ void tile_all_body(const TileArgs& a) {
             }
         }
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < 2; ++rb) {
+            na[rb] = nb[rb];
 #pragma unroll
             for (int f = 0; f < P::kBlocks; ++f) xa[rb][f] = xb[rb][f];
+        }
     }
 }
 

@@ -112,8 +112,8 @@ def test_bf_errors(rbc):
     with pytest.raises(rbc.RbcError) as e:
         rbc.bf_search(Q, X, 0)
     assert e.value.status == -1
-    with pytest.raises(rbc.RbcError) as e:
-        rbc.bf_search(Q, X, 1, precision="bf16")
+    with pytest.raises(rbc.RbcError) as e:   # low precision is L2 only
+        rbc.bf_search(Q, X, 1, "l1", precision="bf16")
     assert e.value.status == -4
     idx, dist = rbc.bf_search(Q[:0], X, 2)
     assert idx.shape == (0, 2)

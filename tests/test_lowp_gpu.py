@@ -131,3 +131,35 @@ def test_lowp_rbc_errors(rbc):
     with pytest.raises(rbc.RbcError) as e:
         rbc.rbc_build(torch.randn((500, 16), device="cuda"), 20, metric="l1", precisions=("fp8",))
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("case", [("sub16", 200000, 3000, 128), ("sub8", 100000, 1500, 64),
+                                  ("sub16", 5000, 7, 128)], ids=["sub16", "sub8", "tiny"])
+def test_fp8_cascade(rbc, orc, case):
+    """FP8 queries whose certificate fails are re-ranked by the fp32 tile
+    (a launch sized on the device from the failure count) and stay exact."""
+    import torch
+
+    name, n, m, d = case
+    X, Q = datagen.database(name, n), datagen.queries(name, m)
+    for k in (10, 1):
+        idx, dist, approx, st = _run(rbc, Q, X, k, "fp8")
+        assert_knn_parity(idx, dist, Q, X, k, "l2", orc)
+        print("fp8 %s k=%d cascade %d fallback %d" % (name, k, st[rbc.STAT_CASCADE],
+                                                      st[rbc.STAT_FALLBACK]))
+        if k == 10 and m >= 1000:
+            assert st[rbc.STAT_CASCADE] > 0        # the case the cascade exists for
+        assert st[rbc.STAT_FALLBACK] <= max(1, st[rbc.STAT_CASCADE] // 100)
+    # the same through an index (the cascade runs over the index rows)
+    Xd, Qd = _dev(X), _dev(Q)
+    ix = rbc.rbc_build(Xd, max(1, int(np.sqrt(n))), seed=3, precisions=("fp8",))
+    try:
+        stats = rbc.new_stats()
+        idx, dist = rbc.rbc_search(ix, Qd, 10, precision="fp8", stats=stats)
+        torch.cuda.synchronize()
+        assert_knn_parity(idx.cpu().numpy(), dist.cpu().numpy(), Q, X, 10, "l2", orc)
+        st = stats.cpu().numpy()
+        print("rbc fp8 %s k=10 cascade %d fallback %d" % (name, st[rbc.STAT_CASCADE],
+                                                          st[rbc.STAT_FALLBACK]))
+    finally:
+        ix.free()
