@@ -199,6 +199,19 @@ int rbc_index_info(const rbc_index* index, int64_t* n, int32_t* d, int64_t* n_r,
 int rbc_index_export(const rbc_index* index, int64_t* rep_idx, double* psi,
                      int64_t* list_off, int64_t* list_ids);
 
+/*
+ * rbc_index_export_order -- exact mode: the order of the rows inside each
+ * list, to HOST buffers (either may be NULL).  own[n] (float32, in list_ids
+ * order) is the distance of each row to its list's representative as the
+ * build computed it (float32 re-score, float64 on near ties); every list r
+ * with sorted[r] == 1 holds its rows in ascending (own, id) order, so the
+ * rows of a list whose distance to the representative lies in a band form
+ * one contiguous range (the triangle-inequality truncation of a list scan,
+ * Sec. 5.2).  Lists longer than 8192 rows keep id order (sorted[r] == 0).
+ * RBC_EUNSUPPORTED for one-shot indexes.  Synchronises the device.
+ */
+int rbc_index_export_order(const rbc_index* index, float* own, int32_t* sorted);
+
 /* rbc_free -- release an index (NULL is a no-op).  Synchronises the device. */
 void rbc_free(rbc_index* index);
 

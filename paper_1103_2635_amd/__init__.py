@@ -71,6 +71,7 @@ def lib():
                                      ctypes.POINTER(_I64), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_I32), ctypes.POINTER(_SZ)]
         L.rbc_index_export.argtypes = [_P, _P, _P, _P, _P]
+        L.rbc_index_export_order.argtypes = [_P, _P, _P]
         L.rbc_free.argtypes = [_P]
         L.rbc_free.restype = None
         L.rbc_timer_enable.argtypes = [ctypes.c_int]
@@ -193,6 +194,16 @@ class Index:
         ids = np.empty(int(off[-1]), np.int64)
         _check(lib().rbc_index_export(self.handle, None, None, None, ids.ctypes.data))
         return {"rep_idx": rep, "psi": psi, "list_off": off, "list_ids": ids}
+
+    def export_order(self):
+        """Exact mode: (own distances in list order, per-list sorted flags)."""
+        import numpy as np
+
+        inf = self.info()
+        own = np.empty(inf["n"], np.float32)
+        srt = np.empty(inf["n_r"], np.int32)
+        _check(lib().rbc_index_export_order(self.handle, own.ctypes.data, srt.ctypes.data))
+        return own, srt.astype(bool)
 
     def free(self):
         if self._h:

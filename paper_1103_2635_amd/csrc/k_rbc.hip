@@ -537,6 +537,78 @@ hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int
     return hipGetLastError();
 }
 
+// ------------------------------------------------ segmented sort (LDS)
+// Segment s = vals[off[s] .. off[s + 1]) is reordered by ascending key, ties
+// kept in their current order: key of the element at position j is
+// keys[vals[j]] (ldk == 0) or keys[vals[j] * ldk + s] (ldk > 0).  Keys are
+// non-negative floats (their bit patterns order like the values).  One
+// workgroup per segment, bitonic network over (key bits, position) in LDS;
+// segments longer than kSegCap are left as they are and flagged 0 in
+// sorted (optional), the others 1.
+__global__ __launch_bounds__(1024) void seg_sort_kernel(const int32_t* off, int32_t* vals,
+                                                        const float* keys, int64_t ldk,
+                                                        int32_t* sorted) {
+    __shared__ uint64_t key[kSegCap];
+    const int sg = blockIdx.x;
+    const int b = off[sg];
+    const int len = off[sg + 1] - b;
+    if (len > kSegCap) {
+        if (sorted && threadIdx.x == 0) sorted[sg] = 0;
+        return;
+    }
+    if (sorted && threadIdx.x == 0) sorted[sg] = 1;
+    if (len <= 1) return;
+    int size = 1;
+    while (size < len) size <<= 1;
+    for (int i = threadIdx.x; i < size; i += blockDim.x) {
+        uint64_t kv = ~0ull;
+        if (i < len) {
+            const int64_t v = vals[b + i];
+            const float f = ldk > 0 ? keys[v * ldk + sg] : keys[v];
+            kv = ((uint64_t)__float_as_uint(f) << 32) | (uint32_t)i;
+        }
+        key[i] = kv;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= size; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < size; i += blockDim.x) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const bool up = (i & kk) == 0;
+                    const uint64_t a = key[i], c = key[p];
+                    if ((a > c) == up) {
+                        key[i] = c;
+                        key[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // gather the values in key order (all reads before any write)
+    int32_t got[kSegCap / 1024];
+#pragma unroll
+    for (int t = 0; t < kSegCap / 1024; ++t) {
+        const int i = threadIdx.x + t * 1024;
+        got[t] = i < len ? vals[b + (int)(key[i] & 0xffffffffu)] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kSegCap / 1024; ++t) {
+        const int i = threadIdx.x + t * 1024;
+        if (i < len) vals[b + i] = got[t];
+    }
+}
+
+hipError_t launch_seg_sort(const int32_t* off, int32_t nseg, int32_t* vals, const float* keys,
+                           int64_t ldk, int32_t* sorted, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(seg_sort_kernel, dim3(nseg), dim3(1024), 0, st, off, vals, keys, ldk,
+                       sorted);
+    return hipGetLastError();
+}
+
 // keep_rq[r][q] = (lrank[q][r] >= 0), through 64 x 64 LDS tiles so that both
 // the reads and the writes are contiguous.
 __global__ __launch_bounds__(256) void keep_transpose_kernel(const int32_t* lrank, int32_t m,

@@ -36,6 +36,8 @@ struct rbc_index {
     float* R = nullptr;          // representatives, n_r x ld
     double* psi = nullptr;       // list radii
     uint32_t* norms_max = nullptr;  // xstat of Xp: [0] max row norm bits, [1..3] value flags
+    float* own = nullptr;           // exact mode: rho(x, owner) of each row of Xp
+    int32_t* lsorted = nullptr;     // exact mode: list r sorted by own (1) or not (0)
     // quantised copies of Xp for low-precision searches, indexed by rbc_precision
     struct Quant {
         void* X = nullptr;        // rows x dq elements (bf16) or bytes (fp8 e4m3)
@@ -154,6 +156,8 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     if ((rc = dev_alloc(ix, &ix->xn, n))) return rc;
     if ((rc = dev_alloc(ix, &ix->ids, n))) return rc;
     if ((rc = dev_alloc(ix, &ix->norms_max, 4))) return rc;
+    if ((rc = dev_alloc(ix, &ix->own, n))) return rc;
+    if ((rc = dev_alloc(ix, &ix->lsorted, n_r))) return rc;
     ix->rows = n;
 
     Scratch s;
@@ -186,10 +190,16 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
         return rc;
     if ((rc = check(launch_narrow(own64, n, owner, st), "owners"))) return rc;
 
-    // lists: stable counting sort of the points by owner
+    // lists: stable counting sort of the points by owner, then each list by
+    // the distance to its owner (ties in id order), kept with the index
     if ((rc = check(launch_csort(owner, n, (int32_t)n_r, cnt, perm, ix->list_off, st), "sort")))
         return rc;
+    if ((rc = check(launch_seg_sort(ix->list_off, (int32_t)n_r, perm, ownd, 0, ix->lsorted, st),
+                    "sort lists")))
+        return rc;
     if ((rc = check(launch_gather_rows(X, ldx, d, perm, n, ix->Xp, ld, ix->ids, st), "gather Xp")))
+        return rc;
+    if ((rc = check(launch_gather_rows(ownd, 1, 1, perm, n, ix->own, 1, nullptr, st), "gather own")))
         return rc;
     if ((rc = check(launch_fill_i32((int32_t*)ix->norms_max, 4, 0, st), "clear"))) return rc;
     if ((rc = check(launch_row_norms(ix->Xp, n, ld, d, nullptr, ix->xn, ix->norms_max, st,
@@ -860,6 +870,24 @@ int rbc_index_export(const rbc_index* ix, int64_t* rep_idx, double* psi, int64_t
         if (list_ids &&
             (rc = check(hipMemcpy(list_ids, ix->ids, ix->rows * sizeof(int64_t),
                                   hipMemcpyDeviceToHost), "copy ids")))
+            return rc;
+        return RBC_OK;
+    } catch (...) {
+        return set_err(RBC_EHIP, "unexpected exception");
+    }
+}
+
+int rbc_index_export_order(const rbc_index* ix, float* own, int32_t* sorted) {
+    try {
+        if (!ix) return set_err(RBC_EINVAL, "index is NULL");
+        if (ix->mode != RBC_EXACT) return set_err(RBC_EUNSUPPORTED, "exact-mode indexes only");
+        int rc;
+        if ((rc = check(hipDeviceSynchronize(), "sync"))) return rc;
+        if (own && (rc = check(hipMemcpy(own, ix->own, ix->rows * sizeof(float),
+                                         hipMemcpyDeviceToHost), "copy distances")))
+            return rc;
+        if (sorted && (rc = check(hipMemcpy(sorted, ix->lsorted, ix->n_r * sizeof(int32_t),
+                                            hipMemcpyDeviceToHost), "copy flags")))
             return rc;
         return RBC_OK;
     } catch (...) {

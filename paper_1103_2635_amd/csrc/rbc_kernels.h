@@ -8,6 +8,7 @@ namespace rbc {
 constexpr int kSortBlock = 4096;   // items per block of the stable counting sort
 constexpr int kMaxReps = 16384;    // LDS histogram of the counting sort
 constexpr int kOsCap = 8192;       // one-shot build: candidates per representative (LDS sort)
+constexpr int kSegCap = 8192;      // longest segment of the LDS segmented sort
 
 // Scratch of the one-shot list selection for a chunk of representatives.
 struct OneShotWork {
@@ -70,5 +71,8 @@ hipError_t launch_oneshot_sort(const float* X, int64_t ldx, int32_t d, int32_t m
 hipError_t launch_items_from_offsets(const int32_t* roff, int32_t nr, int32_t isize,
                                      int32_t* ioff, hipStream_t st);
 hipError_t launch_list_offsets(int32_t* off, int32_t nr, int32_t s, hipStream_t st);
+// Stable sort of each segment of vals by a float key (see k_rbc.hip).
+hipError_t launch_seg_sort(const int32_t* off, int32_t nseg, int32_t* vals, const float* keys,
+                           int64_t ldk, int32_t* sorted, hipStream_t st);
 
 }  // namespace rbc

@@ -37,17 +37,51 @@ def _search(rbc, ix, Q, k, **kw):
 
 @pytest.mark.parametrize("metric", ["l2", "l1"])
 def test_build_matches_oracle(rbc, orc, metric):
-    """Ownership lists, their order and the radii psi_r equal the oracle's
-    (psi bit for bit: both sum the float64 terms in the same order)."""
+    """Ownership lists and the radii psi_r equal the oracle's (psi bit for
+    bit: both sum the float64 terms in the same order); inside each list the
+    rows are ordered by their distance to the representative (ties by id),
+    the stored distances agree with float64 ones to 1e-5."""
     X = datagen.database("sub8", 20000)
     reps = datagen.random_reps(20000, 141, seed=5)
     ix = rbc.rbc_build(_dev(X), 141, metric=metric, rep_idx=reps)
     got = ix.export()
+    own, srt = ix.export_order()
     ref = orc.rbc_build_exact(X, reps, metric)
     assert np.array_equal(got["rep_idx"], reps)
     assert np.array_equal(got["list_off"], ref["list_off"])
-    assert np.array_equal(got["list_ids"], ref["list_ids"])
     assert np.array_equal(got["psi"], ref["psi"])
+    off = got["list_off"]
+    assert srt.all()
+    for r in range(141):
+        a, b = off[r], off[r + 1]
+        ids = got["list_ids"][a:b]
+        assert np.array_equal(np.sort(ids), ref["list_ids"][a:b])   # oracle lists are id-ordered
+        key = np.lexsort((ids, own[a:b]))
+        assert np.array_equal(key, np.arange(b - a)), r             # (own, id) ascending
+        rho = orc.rho_pairs(np.repeat(X[reps[r]][None], b - a, 0), X[ids], metric)
+        np.testing.assert_allclose(own[a:b], rho, rtol=1e-5, atol=1e-6)
+        assert abs(rho.max() - got["psi"][r]) <= 1e-12 * max(1.0, got["psi"][r])
+    ix.free()
+
+
+def test_long_lists_stay_unsorted_and_exact(rbc, orc):
+    """A list longer than the in-LDS sort holds (8192 rows) keeps id order,
+    is flagged, and the search scans it whole (same answers)."""
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((30000, 16)).astype(np.float32)
+    X[:12000] *= 0.01                       # a dense blob owned by one representative
+    reps = np.array([0, 12000, 15000, 20000, 25000], np.int64)
+    ix = rbc.rbc_build(_dev(X), 5, rep_idx=reps)
+    own, srt = ix.export_order()
+    off = ix.export()["list_off"]
+    sizes = np.diff(off)
+    assert (sizes > 8192).any()
+    assert np.array_equal(srt, sizes <= 8192)
+    Q = np.concatenate([X[:100] + 0.001, rng.standard_normal((100, 16)).astype(np.float32)])
+    for k in (1, 10):
+        idx, dist, st = _search(rbc, ix, Q, k)
+        assert_knn_parity(idx, dist, Q, X, k, "l2", orc)
+    ix.free()
 
 
 CASES = [  # (workload, n, m, n_r)
