@@ -89,8 +89,9 @@ typedef enum {
 /* Per-call search options.  Pass NULL for the defaults. */
 typedef struct rbc_search_opts {
     int32_t precision;  /* rbc_precision; default RBC_FP32 */
-    int32_t shortlist;  /* per-query shortlist length c (0 = automatic); rounded up
-                           to one of 4, 8, 16, 32, 64 and at least k + 3 */
+    int32_t shortlist;  /* per-query shortlist length c (0 = automatic: at least
+                           k + 3; at least 8 for RBC_BF16, 32 for RBC_FP8_E4M3);
+                           rounded up to one of 4, 8, 16, 32, 64, and >= k + 3 */
     int32_t splits;     /* database splits per query block (0 = automatic) */
     int32_t flags;      /* reserved, must be 0 */
     int64_t* dev_stats; /* optional DEVICE array of RBC_STATS_LEN int64 counters */

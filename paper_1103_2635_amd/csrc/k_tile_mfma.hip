@@ -17,17 +17,22 @@ struct Fp32Policy {
     typedef f4 QFrag;
     typedef f4 XFrag;
     static constexpr int kBlocks = KS;
+    // Runs past the last feature read the row's first run and are zeroed by a
+    // select: every load is issued unconditionally, so the compiler can count
+    // the outstanding loads exactly and the prefetch stays one block ahead.
     static __device__ __forceinline__ void load_q(f4& q, const TileArgs& a, int row, int s, int g) {
         const int f = 16 * s + 4 * g;
-        f4 v = {0.f, 0.f, 0.f, 0.f};
-        if (f < a.d) v = *(const f4*)(a.Q + (int64_t)row * a.ldq + f);
-        q = v * -2.0f;
+        const bool in = f < a.d;
+        const f4 v = *(const f4*)(a.Q + (int64_t)row * a.ldq + (in ? f : 0));
+        const f4 z = {0.f, 0.f, 0.f, 0.f};
+        q = (in ? v : z) * -2.0f;
     }
     static __device__ __forceinline__ void load_x(f4& x, const TileArgs& a, int row, int s, int g) {
         const int f = 16 * s + 4 * g;
-        f4 v = {0.f, 0.f, 0.f, 0.f};
-        if (f < a.d) v = *(const f4*)(a.X + (int64_t)row * a.ldx + f);
-        x = v;
+        const bool in = f < a.d;
+        const f4 v = *(const f4*)(a.X + (int64_t)row * a.ldx + (in ? f : 0));
+        const f4 z = {0.f, 0.f, 0.f, 0.f};
+        x = in ? v : z;
     }
     static __device__ __forceinline__ f4 mma(const f4& x, const f4& q, f4 c) {
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], q[0], c, 0, 0, 0);

@@ -58,8 +58,12 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
     p->repack_q = (d % 4) != 0 || (ldq % 4) != 0;
     p->repack_x = (d % 4) != 0 || (ldx % 4) != 0;
     p->prec = prec;
-    // low precision ranks on quantised rows: a longer default shortlist (32)
-    p->c = shortlist_len(k, opts && opts->shortlist ? opts->shortlist : (prec != RBC_FP32 ? 32 : 0));
+    // Default shortlist: fp32 the shortest with c >= k + 3; bf16 at least 8
+    // (its ranking error is ~0.3 %, so a short list still certifies, and the
+    // insert cost grows with c); fp8 32 (an error of several percent needs the
+    // wider margin, or most queries go to the fp32 cascade).
+    const int cdef = prec == RBC_FP8_E4M3 ? 32 : (prec == RBC_BF16 ? 8 : 0);
+    p->c = shortlist_len(k, opts && opts->shortlist ? opts->shortlist : cdef);
     p->ks = (d + 15) / 16;
     if (p->c == 0 || p->ks > kMaxKS) {
         p->path = kPathExact;

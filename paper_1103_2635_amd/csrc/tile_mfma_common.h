@@ -104,13 +104,54 @@ __device__ __forceinline__ void refresh_bounds(float (&wq)[4], const TopC<C>& to
     for (int qb = 0; qb < 4; ++qb) wq[qb] = __shfl(w, 16 * qb + c16);
 }
 
+// One 32-row block: the values, the min-filter, and (only when some lane
+// may insert) the transpose and the pushes.
+template <class P, int C>
+__device__ __forceinline__ void scan_block(const typename P::QFrag (&qf)[4][P::kBlocks],
+                                           const typename P::XFrag (&x)[2][P::kBlocks],
+                                           const f4 (&nr)[2], int base, int r1, bool act,
+                                           TopC<C>& top, float (&wq)[4], float* tb, int lane) {
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    f4 acc[2][4];
+    tile_step<P>(acc, qf, x, nr, base, r1, g);
+    bool need = false;
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+        const float m0 = fminf(fminf(acc[0][qb][0], acc[0][qb][1]), fminf(acc[0][qb][2], acc[0][qb][3]));
+        const float m1 = fminf(fminf(acc[1][qb][0], acc[1][qb][1]), fminf(acc[1][qb][2], acc[1][qb][3]));
+        need |= fminf(m0, m1) < wq[qb];
+    }
+    if (__ballot(need) != 0ull) {
+        // transpose: element (query 16 qb + c16, row 16 rb + 4 g + i)
+        wave_lds_sync();
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+                *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
+        wave_lds_sync();
+        f4 vals[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) vals[t] = *(const f4*)(tb + lane * kTStride + 4 * t);
+        if (act) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
+        }
+        refresh_bounds<C>(wq, top, act, c16);
+    }
+}
+
 // Scan database rows [r0, r1) for the wavefront's 64 queries; lanes with act
 // push their values into top.  A 32-row block whose values all lie at or
 // above their query's bound cannot change any shortlist, so it is skipped
 // after a min-reduction in the MFMA layout; otherwise the block goes through
 // the LDS transpose and every value is pushed (the pushes, and so the
-// shortlists, are those of the plain scan).  Fragments and norms of the next
-// block are loaded while the current one is used.
+// shortlists, are those of the plain scan).  Two fragment buffers alternate:
+// while one block is scored, the next block's fragments and norms load into
+// the other, issued before the block's MFMAs, with no register copies.
 template <class P, int C>
 __device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[4][P::kBlocks],
                                           const TileArgs& a, int r0, int r1, bool act,
@@ -119,52 +160,28 @@ __device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[4][P::kB
     const int c16 = lane & 15;
     float wq[4];
     refresh_bounds<C>(wq, top, act, c16);
-    typename P::XFrag xa[2][P::kBlocks];
-    f4 na[2];
+    typename P::XFrag xa[2][P::kBlocks], xb[2][P::kBlocks];
+    f4 na[2], nb[2];
     load_xfrags<P>(xa, a, r0, c16, g);
     load_norms(na, a.xn, r0, r1, g);
-    for (int base = r0; base < r1; base += kRowsMfma) {
-        typename P::XFrag xb[2][P::kBlocks];
-        f4 nb[2];
-        const int next = base + kRowsMfma;
-        const int nbase = next < r1 ? next : base;
+    int base = r0;
+    for (;;) {
+        int next = base + kRowsMfma;
+        int nbase = next < r1 ? next : base;
         load_xfrags<P>(xb, a, nbase, c16, g);
         load_norms(nb, a.xn, nbase, r1, g);
-        f4 acc[2][4];
-        tile_step<P>(acc, qf, xa, na, base, r1, g);
-        bool need = false;
-#pragma unroll
-        for (int qb = 0; qb < 4; ++qb) {
-            const float m0 = fminf(fminf(acc[0][qb][0], acc[0][qb][1]), fminf(acc[0][qb][2], acc[0][qb][3]));
-            const float m1 = fminf(fminf(acc[1][qb][0], acc[1][qb][1]), fminf(acc[1][qb][2], acc[1][qb][3]));
-            need |= fminf(m0, m1) < wq[qb];
-        }
-        if (__ballot(need) != 0ull) {
-            // transpose: element (query 16 qb + c16, row 16 rb + 4 g + i)
-            wave_lds_sync();
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int qb = 0; qb < 4; ++qb)
-                    *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
-            wave_lds_sync();
-            f4 vals[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) vals[t] = *(const f4*)(tb + lane * kTStride + 4 * t);
-            if (act) {
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
-            }
-            refresh_bounds<C>(wq, top, act, c16);
-        }
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-            na[rb] = nb[rb];
-#pragma unroll
-            for (int f = 0; f < P::kBlocks; ++f) xa[rb][f] = xb[rb][f];
-        }
+        __builtin_amdgcn_sched_barrier(0);
+        scan_block<P, C>(qf, xa, na, base, r1, act, top, wq, tb, lane);
+        base = next;
+        if (base >= r1) break;
+        next = base + kRowsMfma;
+        nbase = next < r1 ? next : base;
+        load_xfrags<P>(xa, a, nbase, c16, g);
+        load_norms(na, a.xn, nbase, r1, g);
+        __builtin_amdgcn_sched_barrier(0);
+        scan_block<P, C>(qf, xb, nb, base, r1, act, top, wq, tb, lane);
+        base = next;
+        if (base >= r1) break;
     }
 }
 
