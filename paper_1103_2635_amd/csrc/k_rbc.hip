@@ -23,10 +23,34 @@ __global__ void gather_rows_kernel(const float* A, int64_t lda, int32_t d, const
     }
 }
 
+// Float4 form (d, lda, ldo multiples of 4, A 16-byte aligned): one float4
+// per thread.
+__global__ void gather_rows4_kernel(const float* A, int64_t lda4, int32_t d4, const int32_t* rows,
+                                    int64_t nrows, float* out, int64_t ldo4, int64_t* ids_out) {
+    const int64_t total = nrows * ldo4;
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ldo4;
+        const int64_t c = e - i * ldo4;
+        const int64_t src = rows[i];
+        ((f4*)out)[e] = c < d4 ? ((const f4*)A)[src * lda4 + c] : z;
+        if (c == 0 && ids_out) ids_out[i] = src;
+    }
+}
+
 hipError_t launch_gather_rows(const float* A, int64_t lda, int32_t d, const int32_t* rows,
                               int64_t nrows, float* out, int64_t ldo, int64_t* ids_out,
                               hipStream_t st) {
     if (nrows <= 0) return hipSuccess;
+    if (d % 4 == 0 && lda % 4 == 0 && ldo % 4 == 0 && ((uintptr_t)A & 15) == 0 &&
+        ((uintptr_t)out & 15) == 0) {
+        int64_t blocks = (nrows * (ldo / 4) + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(gather_rows4_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A,
+                           lda / 4, d / 4, rows, nrows, out, ldo / 4, ids_out);
+        return hipGetLastError();
+    }
     int64_t blocks = (nrows * ldo + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, lda, d,
@@ -227,65 +251,100 @@ hipError_t launch_csort(const int32_t* keys, int64_t n, int32_t nk, int32_t* cnt
 }
 
 // ------------------------------------------------------------- list radii
-// psi_r = max over the points x owned by r of rho(x, r) (Sec. 4), in float64
-// with the fixed summation order.  A first pass takes the fp32 maximum per
-// list (16 lanes per point, any order); only points whose fp32 distance is
-// within the fp32 error of that maximum can hold the float64 maximum, and only
-// they are scored again in float64.  Maxima are taken on the bit patterns of
-// non-negative floats / doubles, which order like the values.
-__global__ __launch_bounds__(256) void psi32_kernel(const float* X, int64_t ldx, int32_t d,
-                                                    int32_t metric, int64_t n,
-                                                    const int32_t* owner, const float* R,
-                                                    int64_t ldr, float* dist32,
-                                                    uint32_t* max32) {
-    const int sub = threadIdx.x & 15;
-    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
-    float s = 0.f;
-    int32_t r = 0;
-    if (i < n) {
-        r = owner[i];
-        const float* xp = X + i * ldx;
-        const float* rp = R + (int64_t)r * ldr;
-        for (int f = sub; f < d; f += 16) {
-            const float t = xp[f] - rp[f];
-            s = metric == 0 ? __builtin_fmaf(t, t, s) : s + __builtin_fabsf(t);
+// psi_r from the lists sorted by own = rho(x, r) (the fp32 distances of the
+// ownership search, relative error <= delta): the float64 maximum can only
+// be held by rows with own >= max(own) (1 - 2 delta), a suffix of a sorted
+// list (unsorted lists are screened whole); those rows are scored again in
+// float64 (the fixed order of rho_fp64) and psi_r is their maximum, equal to
+// the maximum over the whole list.  One workgroup per list; empty lists get 0.
+__global__ __launch_bounds__(256) void psi_own_kernel(const float* Xp, int64_t ld, int32_t d,
+                                                      int32_t metric, const float* own,
+                                                      const int32_t* list_off,
+                                                      const int32_t* lsorted, const float* R,
+                                                      int64_t ldr, double delta, double* psi) {
+    __shared__ float s_max[4];
+    __shared__ double s_psi[4];
+    const int r = blockIdx.x;
+    const int b = list_off[r], e = list_off[r + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (b == e) {
+        if (tid == 0) psi[r] = 0.0;
+        return;
+    }
+    const bool sorted = lsorted[r] != 0;
+    float m32 = 0.f;
+    if (sorted) {
+        m32 = own[e - 1];
+    } else {
+        for (int j = b + tid; j < e; j += 256) m32 = fmaxf(m32, own[j]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m32 = fmaxf(m32, __shfl_xor(m32, off));
+        if (lane == 0) s_max[wave] = m32;
+        __syncthreads();
+        m32 = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
+    }
+    const double thr = (double)m32 * (1.0 - 2.0 * delta);
+    const float* rp = R + (int64_t)r * ldr;
+    double best = 0.0;
+    if (sorted) {
+        for (int j = e - 1 - tid; j >= b; j -= 256) {
+            if ((double)own[j] < thr) break;
+            best = fmax(best, rho_fp64(Xp + (int64_t)j * ld, rp, d, metric));
         }
+    } else {
+        for (int j = b + tid; j < e; j += 256)
+            if ((double)own[j] >= thr) best = fmax(best, rho_fp64(Xp + (int64_t)j * ld, rp, d, metric));
     }
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
-    if (i < n && sub == 0) {
-        const float v = metric == 0 ? __builtin_sqrtf(s) : s;
-        dist32[i] = v;
-        atomicMax(max32 + r, __float_as_uint(v));
+    for (int off = 32; off >= 1; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+    if (lane == 0) s_psi[wave] = best;
+    __syncthreads();
+    if (tid == 0) psi[r] = fmax(fmax(s_psi[0], s_psi[1]), fmax(s_psi[2], s_psi[3]));
+}
+
+hipError_t launch_psi_own(const float* Xp, int64_t ld, int32_t d, int32_t metric, const float* own,
+                          const int32_t* list_off, const int32_t* lsorted, const float* R,
+                          int64_t ldr, int32_t nr, double* psi, hipStream_t st) {
+    const double delta = 2.0 * (d + 2) * 5.9604644775390625e-8;
+    hipLaunchKernelGGL(psi_own_kernel, dim3(nr), dim3(256), 0, st, Xp, ld, d, metric, own,
+                       list_off, lsorted, R, ldr, delta, psi);
+    return hipGetLastError();
+}
+
+// xn[i] = qn[perm[i]] (the squared norms the ownership search computed for
+// the rows of X), the largest norm as float bits (atomic max, one per
+// workgroup) and a copy of the 3 value-flag words.
+__global__ __launch_bounds__(256) void gather_norms_kernel(const float* qn, const int32_t* perm,
+                                                           int64_t n, float* xn, uint32_t* maxbits,
+                                                           const uint32_t* flags_in,
+                                                           uint32_t* flags_out) {
+    __shared__ float wmax[4];
+    float m = 0.f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = qn[perm[i]];
+        xn[i] = v;
+        m = fmaxf(m, __builtin_sqrtf(v));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(maxbits, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
+        if (blockIdx.x == 0)
+            for (int w = 0; w < 3; ++w) flags_out[w] = flags_in[w];
     }
 }
 
-__global__ void psi64_kernel(const float* X, int64_t ldx, int32_t d, int32_t metric, int64_t n,
-                             const int32_t* owner, const float* R, int64_t ldr,
-                             const float* dist32, const uint32_t* max32, double delta,
-                             unsigned long long* psi_bits) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t r = owner[i];
-    const double m32 = (double)__uint_as_float(max32[r]);
-    if ((double)dist32[i] < m32 * (1.0 - 2.0 * delta)) return;
-    const double v = rho_fp64(X + i * ldx, R + (int64_t)r * ldr, d, metric);
-    atomicMax(psi_bits + r, (unsigned long long)__double_as_longlong(v));
-}
-
-hipError_t launch_psi(const float* X, int64_t ldx, int32_t d, int32_t metric, int64_t n,
-                      const int32_t* owner, const float* R, int64_t ldr, int32_t nr,
-                      float* dist32, uint32_t* max32, double* psi, hipStream_t st) {
-    hipError_t e;
-    if ((e = launch_fill_i32((int32_t*)max32, nr, 0, st)) != hipSuccess) return e;
-    if ((e = launch_fill_i32((int32_t*)psi, 2 * (int64_t)nr, 0, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(psi32_kernel, dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, st, X,
-                       ldx, d, metric, n, owner, R, ldr, dist32, max32);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const double delta = 2.0 * (d + 2) * 5.9604644775390625e-8;
-    hipLaunchKernelGGL(psi64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ldx,
-                       d, metric, n, owner, R, ldr, (const float*)dist32, (const uint32_t*)max32,
-                       delta, (unsigned long long*)psi);
+hipError_t launch_gather_norms(const float* qn, const int32_t* perm, int64_t n, float* xn,
+                               uint32_t* maxbits, const uint32_t* flags_in, uint32_t* flags_out,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(gather_norms_kernel, dim3((unsigned)blocks), dim3(256), 0, st, qn, perm, n,
+                       xn, maxbits, flags_in, flags_out);
     return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <unordered_set>
 #include <vector>
@@ -94,6 +96,59 @@ struct Scratch {
     }
 };
 
+// Device memory of an index as one allocation: add() records the arrays,
+// commit() allocates their sum (256-byte aligned pieces) and hands them out.
+struct Layout {
+    std::vector<std::pair<void**, size_t>> items;
+    template <class T>
+    void add(T** p, int64_t count) {
+        items.push_back({(void**)p, (size_t)std::max<int64_t>(count, 1) * sizeof(T)});
+    }
+    int commit(rbc_index* ix) {
+        size_t total = 0;
+        for (auto& it : items) total += (it.second + 255) & ~(size_t)255;
+        void* base = nullptr;
+        if (hipMalloc(&base, total) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(RBC_ENOMEM, "device allocation of %zu bytes failed", total);
+        }
+        ix->allocs.push_back(base);
+        ix->bytes += total;
+        char* c = (char*)base;
+        for (auto& it : items) {
+            *it.first = c;
+            c += (it.second + 255) & ~(size_t)255;
+        }
+        items.clear();
+        return RBC_OK;
+    }
+};
+
+// Scratch of exact builds, kept per device between builds (grown when a
+// larger build needs more) so that a build allocates only its index.
+// Builds hold g_build_mu from the first use of the scratch to their final
+// synchronisation; searches never touch it.
+std::mutex g_build_mu;
+std::map<int, std::pair<void*, size_t>> g_build_scratch;
+
+int build_scratch(size_t bytes, char** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_err(RBC_EHIP, "hipGetDevice failed");
+    auto& e = g_build_scratch[dev];
+    if (e.second < bytes) {
+        if (e.first) (void)hipFree(e.first);
+        e.first = nullptr;
+        e.second = 0;
+        if (hipMalloc(&e.first, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(RBC_ENOMEM, "device allocation of %zu bytes failed", bytes);
+        }
+        e.second = bytes;
+    }
+    *out = (char*)e.first;
+    return RBC_OK;
+}
+
 uint64_t splitmix64(uint64_t& s) {
     uint64_t z = (s += 0x9e3779b97f4a7c15ull);
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -149,42 +204,48 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     const int64_t n = ix->n, n_r = ix->n_r, ld = ix->ld;
     const int32_t d = ix->d;
     int rc;
-    if ((rc = dev_alloc(ix, &ix->R, n_r * ld))) return rc;
-    if ((rc = dev_alloc(ix, &ix->psi, n_r))) return rc;
-    if ((rc = dev_alloc(ix, &ix->list_off, n_r + 1))) return rc;
-    if ((rc = dev_alloc(ix, &ix->Xp, n * ld))) return rc;
-    if ((rc = dev_alloc(ix, &ix->xn, n))) return rc;
-    if ((rc = dev_alloc(ix, &ix->ids, n))) return rc;
-    if ((rc = dev_alloc(ix, &ix->norms_max, 4))) return rc;
-    if ((rc = dev_alloc(ix, &ix->own, n))) return rc;
-    if ((rc = dev_alloc(ix, &ix->lsorted, n_r))) return rc;
+    Layout lay;
+    lay.add(&ix->R, n_r * ld);
+    lay.add(&ix->psi, n_r);
+    lay.add(&ix->list_off, n_r + 1);
+    lay.add(&ix->Xp, n * ld);
+    lay.add(&ix->xn, n);
+    lay.add(&ix->ids, n);
+    lay.add(&ix->norms_max, 4);
+    lay.add(&ix->own, n);
+    lay.add(&ix->lsorted, n_r);
+    if ((rc = lay.commit(ix))) return rc;
     ix->rows = n;
 
-    Scratch s;
+    // ownership: BF(X, R) with k = 1 (ties to the lower representative position)
+    BfPlan p;
+    if ((rc = make_bf_plan(n, n_r, d, ldx, ld, ix->metric, 1, nullptr, &p))) return rc;
     int32_t *reps = nullptr, *owner = nullptr, *perm = nullptr, *cnt = nullptr;
     int64_t* own64 = nullptr;
     float* ownd = nullptr;
-    if ((rc = s.take(&reps, n_r)) || (rc = s.take(&owner, n)) || (rc = s.take(&perm, n)) ||
-        (rc = s.take(&cnt, csort_scratch(n, (int32_t)n_r))) || (rc = s.take(&own64, n)) ||
-        (rc = s.take(&ownd, n)))
-        return rc;
+    BfWork w;
+    auto carve = [&](Carver& cv) {
+        reps = cv.take<int32_t>(n_r);
+        owner = cv.take<int32_t>(n);
+        perm = cv.take<int32_t>(n);
+        cnt = cv.take<int32_t>(csort_scratch(n, (int32_t)n_r));
+        own64 = cv.take<int64_t>(n);
+        ownd = cv.take<float>(n);
+        carve_bf(p, n, n_r, cv, &w);
+    };
+    Carver probe(nullptr);
+    carve(probe);
+    std::lock_guard<std::mutex> lock(g_build_mu);
+    char* ws = nullptr;
+    if ((rc = build_scratch(probe.size(), &ws))) return rc;
+    Carver cv(ws);
+    carve(cv);
     std::vector<int32_t> reps32(ix->rep_host.begin(), ix->rep_host.end());
     if ((rc = check(hipMemcpyAsync(reps, reps32.data(), n_r * sizeof(int32_t),
                                    hipMemcpyHostToDevice, st), "copy representatives")))
         return rc;
     if ((rc = check(launch_gather_rows(X, ldx, d, reps, n_r, ix->R, ld, nullptr, st), "gather R")))
         return rc;
-
-    // ownership: BF(X, R) with k = 1 (ties to the lower representative position)
-    BfPlan p;
-    if ((rc = make_bf_plan(n, n_r, d, ldx, ld, ix->metric, 1, nullptr, &p))) return rc;
-    Carver probe(nullptr);
-    BfWork w;
-    carve_bf(p, n, n_r, probe, &w);
-    char* ws = nullptr;
-    if ((rc = s.take(&ws, (int64_t)probe.size()))) return rc;
-    Carver cv(ws);
-    carve_bf(p, n, n_r, cv, &w);
     if ((rc = run_bf(p, X, n, ldx, ix->R, n_r, ld, nullptr, nullptr, nullptr, own64, ownd, w,
                      nullptr, st)))
         return rc;
@@ -202,12 +263,18 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     if ((rc = check(launch_gather_rows(ownd, 1, 1, perm, n, ix->own, 1, nullptr, st), "gather own")))
         return rc;
     if ((rc = check(launch_fill_i32((int32_t*)ix->norms_max, 4, 0, st), "clear"))) return rc;
-    if ((rc = check(launch_row_norms(ix->Xp, n, ld, d, nullptr, ix->xn, ix->norms_max, st,
-                                     ix->norms_max + 1), "norms")))
+    if (p.path == kPathMfma) {
+        // the ownership search already has ||x||^2 and the value flags of X
+        if ((rc = check(launch_gather_norms(w.qn, perm, n, ix->xn, ix->norms_max,
+                                            (const uint32_t*)w.counters + 5, ix->norms_max + 1,
+                                            st), "norms")))
+            return rc;
+    } else if ((rc = check(launch_row_norms(ix->Xp, n, ld, d, nullptr, ix->xn, ix->norms_max, st,
+                                            ix->norms_max + 1), "norms"))) {
         return rc;
-    // ownd (the BF distances) and cnt are free again: reuse them as psi scratch
-    if ((rc = check(launch_psi(X, ldx, d, ix->metric, n, owner, ix->R, ld, (int32_t)n_r, ownd,
-                               (uint32_t*)cnt, ix->psi, st), "psi")))
+    }
+    if ((rc = check(launch_psi_own(ix->Xp, ld, d, ix->metric, ix->own, ix->list_off, ix->lsorted,
+                                   ix->R, ld, (int32_t)n_r, ix->psi, st), "psi")))
         return rc;
     return check(hipStreamSynchronize(st), "build");
 }

@@ -35,10 +35,6 @@ hipError_t launch_narrow(const int64_t* in, int64_t n, int32_t* out, hipStream_t
 // cnt needs csort_scratch(n, nk) int32.
 hipError_t launch_csort(const int32_t* keys, int64_t n, int32_t nk, int32_t* cnt, int32_t* perm,
                         int32_t* offsets, hipStream_t st);
-// dist32: n floats, max32: nr uint32 of scratch
-hipError_t launch_psi(const float* X, int64_t ldx, int32_t d, int32_t metric, int64_t n,
-                      const int32_t* owner, const float* R, int64_t ldr, int32_t nr,
-                      float* dist32, uint32_t* max32, double* psi, hipStream_t st);
 hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, const float* R,
                            int64_t ldr, int32_t nr, int32_t d, float* DR, int64_t ldd,
                            hipStream_t st);
@@ -71,6 +67,14 @@ hipError_t launch_oneshot_sort(const float* X, int64_t ldx, int32_t d, int32_t m
 hipError_t launch_items_from_offsets(const int32_t* roff, int32_t nr, int32_t isize,
                                      int32_t* ioff, hipStream_t st);
 hipError_t launch_list_offsets(int32_t* off, int32_t nr, int32_t s, hipStream_t st);
+// psi_r from the own-sorted lists (float64 re-score of the screened rows).
+hipError_t launch_psi_own(const float* Xp, int64_t ld, int32_t d, int32_t metric, const float* own,
+                          const int32_t* list_off, const int32_t* lsorted, const float* R,
+                          int64_t ldr, int32_t nr, double* psi, hipStream_t st);
+// xn[i] = qn[perm[i]], largest norm (float bits, atomic max), 3 flag words copied.
+hipError_t launch_gather_norms(const float* qn, const int32_t* perm, int64_t n, float* xn,
+                               uint32_t* maxbits, const uint32_t* flags_in, uint32_t* flags_out,
+                               hipStream_t st);
 // Stable sort of each segment of vals by a float key (see k_rbc.hip).
 hipError_t launch_seg_sort(const int32_t* off, int32_t nseg, int32_t* vals, const float* keys,
                            int64_t ldk, int32_t* sorted, hipStream_t st);
