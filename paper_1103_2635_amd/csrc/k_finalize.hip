@@ -199,7 +199,135 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     }
 }
 
+// The same steps for the common case of one list per query (a single
+// database split, no pair lists, c <= 16), with 16 lanes per query and four
+// queries per wavefront: 16 / c lanes re-score each candidate.  Shuffles stay
+// inside a query's 16 lanes; ballots are masked to them.  Used for the
+// ownership search of the build (a million queries) and one-shot searches,
+// where one wavefront per query leaves the kernel latency-bound.
+template <int C>
+__global__ __launch_bounds__(256) void finalize_group_kernel(FinArgs a) {
+    constexpr int G = 16;
+    constexpr int LPC = G / C;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int sh = lane & ~(G - 1);  // first lane of the group in the wavefront
+    const int slot = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    const bool live = slot < a.m;
+    const int qrow = live ? slot : a.m - 1;
+
+    float mv = RBC_INF;
+    int32_t mi = -1;
+    if (live && gl < C) {
+        mv = a.pval[(int64_t)qrow * C + gl];
+        mi = a.pidx[(int64_t)qrow * C + gl];
+    }
+    const bool valid = live && gl < C && mi >= 0 && mv < RBC_INF;
+    const float a_c = __shfl(mv, C - 1, G);
+
+    const float* qp = a.Q + (int64_t)qrow * a.ldq;
+    const int cand = gl / LPC;
+    const int sub = gl % LPC;
+    const int32_t crow = __shfl(mi, cand, G);
+    const bool cvalid = __shfl((int)valid, cand, G) != 0;
+    float part = 0.f;
+    if (cvalid) {
+        const float* cp = a.X + (int64_t)crow * a.ldx;
+        if (a.metric == 0) {
+            for (int f = sub; f < a.d; f += LPC) {
+                const float t = qp[f] - cp[f];
+                part = __builtin_fmaf(t, t, part);
+            }
+        } else {
+            for (int f = sub; f < a.d; f += LPC) part += __builtin_fabsf(qp[f] - cp[f]);
+        }
+    }
+#pragma unroll
+    for (int off = LPC / 2; off >= 1; off >>= 1) part += __shfl_xor(part, off, G);
+    const float s32 = __shfl(part, (gl < C ? gl : 0) * LPC, G);
+    const float* xp = a.X + (int64_t)(valid ? mi : 0) * a.ldx;
+    double rho = RBC_INF_D;
+    if (valid) rho = a.metric == 0 ? __builtin_sqrt((double)s32) : (double)s32;
+
+    const double u = 5.9604644775390625e-8;
+    const double delta = 2.0 * (a.d + 2) * u;
+    const double tol = 2.0 * delta;
+    bool flag = false;
+    for (int i = 0; i < C; ++i) {
+        const double ri = __shfl(rho, i, G);
+        if (i != gl && valid && ri < RBC_INF_D &&
+            __builtin_fabs(ri - rho) <= tol * (ri > rho ? ri : rho))
+            flag = true;
+    }
+    if (flag) rho = rho_fp64(qp, xp, a.d, a.metric);
+    const uint32_t flagged = (uint32_t)((__ballot(flag) >> sh) & 0xffffu);
+
+    const int64_t myid = valid ? (a.id_map ? a.id_map[mi] : (int64_t)mi) : INT64_MAX;
+    int rank = 0;
+    for (int i = 0; i < C; ++i) {
+        const double ri = __shfl(rho, i, G);
+        const int64_t ii = __shfl(myid, i, G);
+        if (i != gl && before(ri, ii, rho, myid)) ++rank;
+    }
+    const int nvalid = __popc((uint32_t)((__ballot(valid) >> sh) & 0xffffu));
+    const uint32_t kth = (uint32_t)((__ballot(valid && rank == a.k - 1) >> sh) & 0xffffu);
+
+    bool ok = live && nvalid >= a.k;
+    if (ok && a_c < RBC_INF) {
+        const double t_k = __shfl(rho, (int)__builtin_ctz(kth), G);
+        double lo;
+        if (a.approx_mode == 0 || a.approx_mode == 2) {
+            const double qn = a.qn[qrow];
+            const double xmax = (double)__uint_as_float(*a.xmax_bits);
+            const double sq = __builtin_sqrt(qn) + xmax;
+            const double e =
+                tile_exact(a.flags_q, a.flags_x, a.d) ? 0.0 : 4.0 * (a.d + 2) * u * sq * sq;
+            const double lo2 = (double)a_c + qn - e;
+            lo = lo2 > 0.0 ? __builtin_sqrt(lo2) : 0.0;
+            if (a.approx_mode == 2)
+                lo -= (double)a.qerr[qrow] + (double)__uint_as_float(*a.xerr_max_bits);
+        } else if (a.metric == 0) {
+            lo = __builtin_sqrt((double)a_c) * (1.0 - delta);
+        } else {
+            lo = (double)a_c * (1.0 - delta);
+        }
+        ok = lo > t_k * (1.0 + delta);
+    }
+
+    if (!live) return;
+    if (!ok) {
+        if (gl == 0) {
+            const int p = atomicAdd(a.fb_count, 1);
+            a.fb_list[p] = qrow;
+        }
+    } else if (valid && rank < a.k) {
+        a.out_idx[(int64_t)qrow * a.k + rank] = myid;
+        a.out_dist[(int64_t)qrow * a.k + rank] = (float)rho;
+        if (a.out_approx) {
+            double ap;
+            if (a.approx_mode == 1)
+                ap = a.metric == 0 ? __builtin_sqrt((double)mv) : (double)mv;
+            else
+                ap = __builtin_sqrt(fmax((double)mv + (double)a.qn[qrow], 0.0));
+            a.out_approx[(int64_t)qrow * a.k + rank] = (float)ap;
+        }
+    }
+    if (a.stats && gl == 0) {
+        if (!ok) atomicAdd((unsigned long long*)&a.stats[a.fail_stat], 1ull);
+        if (flagged) atomicAdd((unsigned long long*)&a.stats[1], (unsigned long long)__popc(flagged));
+    }
+}
+
 hipError_t launch_finalize(int c, const FinArgs& a, hipStream_t st) {
+    if (!a.qoff && a.nsplit == 1 && !a.m_dev && !a.qmap && c <= 16) {
+        const dim3 g16((a.m + 15) / 16);
+        switch (c) {
+            case 4: hipLaunchKernelGGL((finalize_group_kernel<4>), g16, dim3(256), 0, st, a); break;
+            case 8: hipLaunchKernelGGL((finalize_group_kernel<8>), g16, dim3(256), 0, st, a); break;
+            case 16: hipLaunchKernelGGL((finalize_group_kernel<16>), g16, dim3(256), 0, st, a); break;
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((a.m + 3) / 4);
     switch (c) {
         case 4: hipLaunchKernelGGL((finalize_kernel<4>), grid, dim3(256), 0, st, a); break;

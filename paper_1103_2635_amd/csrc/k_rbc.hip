@@ -519,29 +519,45 @@ hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, c
 // nearest database point; it seeds the stage-2 shortlists.
 // Outputs: lrank[q][r] = rank of r among the lists q keeps (-1: pruned),
 // nkept[q], gcup[q].
-__global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd, int32_t m,
-                                                    int32_t nr, int32_t k, int32_t c,
-                                                    double delta, const double* psi,
-                                                    const int32_t* list_off, int32_t* lrank,
-                                                    int32_t* nkept, float* gcup, int64_t* stats) {
-    const int lane = threadIdx.x & 63;
-    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= m) return;
-    const float* row = DR + (int64_t)q * ldd;
-
-    float g1 = RBC_INF;
-    for (int r = lane; r < nr; r += 64) g1 = fminf(g1, row[r]);
+// gamma_1 (the minimum) and the bit patterns of gamma_k and gamma_c: the
+// smallest pattern p with count(v <= p) >= k (c).  V > 0: the lane's values
+// (r = lane + 64 j, j < V) are held in registers (+inf pads), so the 32
+// rounds of the bitwise search read no memory; V = 0: read every round.
+template <int V>
+__device__ __forceinline__ void select_gammas(const float* row, int nr, int k, int c, int lane,
+                                              float& g1, uint32_t& pk, uint32_t& pc) {
+    uint32_t vb[V > 0 ? V : 1];
+    g1 = RBC_INF;
+    if (V > 0) {
+#pragma unroll
+        for (int j = 0; j < (V > 0 ? V : 1); ++j) {
+            const int r = lane + 64 * j;
+            const float v = r < nr ? row[r] : RBC_INF;
+            vb[j] = __float_as_uint(v);
+            g1 = fminf(g1, v);
+        }
+    } else {
+        for (int r = lane; r < nr; r += 64) g1 = fminf(g1, row[r]);
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) g1 = fminf(g1, __shfl_xor(g1, off));
-    // gamma_k and gamma_c: smallest bit pattern p with count(v <= p) >= k (c)
-    uint32_t pk = 0, pc = 0;
+    pk = 0;
+    pc = 0;
     for (int bit = 31; bit >= 0; --bit) {
         const uint32_t tk = pk | (1u << bit), tc = pc | (1u << bit);
         int ck = 0, cc = 0;
-        for (int r = lane; r < nr; r += 64) {
-            const uint32_t b = __float_as_uint(row[r]);
-            ck += b < tk ? 1 : 0;
-            cc += b < tc ? 1 : 0;
+        if (V > 0) {
+#pragma unroll
+            for (int j = 0; j < (V > 0 ? V : 1); ++j) {
+                ck += vb[j] < tk ? 1 : 0;
+                cc += vb[j] < tc ? 1 : 0;
+            }
+        } else {
+            for (int r = lane; r < nr; r += 64) {
+                const uint32_t b = __float_as_uint(row[r]);
+                ck += b < tk ? 1 : 0;
+                cc += b < tc ? 1 : 0;
+            }
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -551,6 +567,21 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
         if (ck < k) pk = tk;
         if (cc < c) pc = tc;
     }
+}
+
+template <int V>
+__global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd, int32_t m,
+                                                    int32_t nr, int32_t k, int32_t c,
+                                                    double delta, const double* psi,
+                                                    const int32_t* list_off, int32_t* lrank,
+                                                    int32_t* nkept, float* gcup, int64_t* stats) {
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= m) return;
+    const float* row = DR + (int64_t)q * ldd;
+    float g1;
+    uint32_t pk, pc;
+    select_gammas<V>(row, nr, k, c, lane, g1, pk, pc);
     const float gk = k <= nr ? __uint_as_float(pk) : RBC_INF;
     const float gc = c <= nr ? __uint_as_float(pc) : RBC_INF;
     const double g1_up = (double)g1 * (1.0 + delta);
@@ -591,8 +622,16 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
 hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
                         double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
                         int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st) {
-    hipLaunchKernelGGL(prune_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, ldd, m, nr, k, c,
-                       delta, psi, list_off, lrank, nkept, gcup, stats);
+    const dim3 grid((m + 3) / 4);
+    if (nr <= 1024)
+        hipLaunchKernelGGL(prune_kernel<16>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
+                           psi, list_off, lrank, nkept, gcup, stats);
+    else if (nr <= 2048)
+        hipLaunchKernelGGL(prune_kernel<32>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
+                           psi, list_off, lrank, nkept, gcup, stats);
+    else
+        hipLaunchKernelGGL(prune_kernel<0>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
+                           psi, list_off, lrank, nkept, gcup, stats);
     return hipGetLastError();
 }
 
