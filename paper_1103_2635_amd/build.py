@@ -25,6 +25,11 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
 
 PER_KS = ["k_tile_mfma.hip", "k_tile_valu.hip"]
 PER_KB = ["k_tile_lowp.hip"]
+# The item queue's ticket is taken by one lane and consumed an item later;
+# the atomic optimizer would read it back at once (it broadcasts the result
+# for a per-lane prefix), which puts the queue latency back on the critical
+# path.  The tile files have no other atomics it would help.
+TILE_FLAGS = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 SINGLE = ["k_util.hip", "k_finalize.hip", "k_rbc.hip", "k_oneshot.hip", "k_quant.hip", "rbc_dispatch.cpp", "rbc_api.cpp",
           "rbc_index.cpp", "rbc_timer.cpp"]
 
@@ -34,11 +39,11 @@ def _units():
     for src in PER_KS:
         for ks in range(1, 9):
             obj = os.path.join(BUILD, "%s.ks%d.o" % (os.path.splitext(src)[0], ks))
-            units.append((src, obj, ["-DRBC_KS=%d" % ks]))
+            units.append((src, obj, ["-DRBC_KS=%d" % ks] + TILE_FLAGS))
     for src in PER_KB:
         for kb in range(1, 5):
             obj = os.path.join(BUILD, "%s.kb%d.o" % (os.path.splitext(src)[0], kb))
-            units.append((src, obj, ["-DRBC_KB=%d" % kb]))
+            units.append((src, obj, ["-DRBC_KB=%d" % kb] + TILE_FLAGS))
     for src in SINGLE:
         if os.path.exists(os.path.join(CSRC, src)):
             units.append((src, os.path.join(BUILD, os.path.splitext(src)[0] + ".o"), []))

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         __syncthreads();
         const int item = s_item;
         if (item >= total) break;
-        const int r = item_rep(a, item);
+        const int r = a.irep ? a.irep[item] : item_rep(a, item);
         const int q_begin = a.roff[r] + (item - a.ioff[r]) * kTileQ;
         const int q_end = a.roff[r + 1];
         const int p = q_begin + (int)threadIdx.x;

@@ -183,4 +183,18 @@ hipError_t launch_cascade_gather(const float* Q, int64_t ldq, int32_t d, int64_t
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void item_rep_kernel(const int32_t* ioff, int32_t nr,
+                                                       int32_t* irep) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nr) return;
+    const int e = ioff[r + 1];
+    for (int i = ioff[r] + (threadIdx.x & 63); i < e; i += 64) irep[i] = r;
+}
+
+hipError_t launch_item_reps(const int32_t* ioff, int32_t nr, int32_t* irep, hipStream_t st) {
+    if (nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(item_rep_kernel, dim3((nr + 3) / 4), dim3(256), 0, st, ioff, nr, irep);
+    return hipGetLastError();
+}
+
 }  // namespace rbc

@@ -51,6 +51,7 @@ struct TileArgs {
     int32_t nsplit;
     const int32_t* item_total;
     int32_t* item_queue;
+    const int32_t* irep;   // item -> representative (null: binary search over ioff)
     const int32_t* ioff;
     const int32_t* roff;
     const int32_t* qlist;
@@ -142,6 +143,8 @@ hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d
                             const int32_t* rowmap, float* out, uint32_t* maxbits,
                             hipStream_t st, uint32_t* flags = nullptr,
                             const int32_t* gate = nullptr);
+// irep[i] = r for every item i of representative r (ioff[r] <= i < ioff[r + 1]).
+hipError_t launch_item_reps(const int32_t* ioff, int32_t nr, int32_t* irep, hipStream_t st);
 hipError_t launch_cascade_gather(const float* Q, int64_t ldq, int32_t d, int64_t m,
                                  const int32_t* list, const int32_t* count, float* Qc,
                                  int64_t ldc, float* qn, int32_t* qmap, int32_t* count_out,

@@ -443,6 +443,7 @@ struct SearchWork {
     int32_t* roff = nullptr;     // n_r + 1
     int32_t* ioff = nullptr;     // n_r + 1
     int32_t* qlist = nullptr;    // up to m * n_r
+    int32_t* irep = nullptr;     // item -> representative
 };
 
 int64_t stage1_ld(int64_t nr) { return (nr + 3) / 4 * 4; }
@@ -459,6 +460,7 @@ struct OneShotSearchWork {
     int32_t* qlist = nullptr;
     int32_t* roff = nullptr;
     int32_t* ioff = nullptr;
+    int32_t* irep = nullptr;
 };
 
 int carve_oneshot(const rbc_index* ix, const BfPlan& p, int64_t m, int64_t ldq, Carver& cv,
@@ -473,6 +475,7 @@ int carve_oneshot(const rbc_index* ix, const BfPlan& p, int64_t m, int64_t ldq, 
     o->qlist = cv.take<int32_t>(m);
     o->roff = cv.take<int32_t>(ix->n_r + 1);
     o->ioff = cv.take<int32_t>(ix->n_r + 1);
+    o->irep = cv.take<int32_t>(m / kWave + ix->n_r + 1);
     if (p.path == kPathExact) {
         carve_bf(p, m, ix->rows, cv, &w->bf);
         return RBC_OK;
@@ -508,6 +511,7 @@ int search_oneshot(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t
         const int32_t isize = p.path == kPathMfma ? kWave : kTileQ;
         if ((rc = check(launch_items_from_offsets(o.roff, nr, isize, o.ioff, st), "items")))
             return rc;
+        if ((rc = check(launch_item_reps(o.ioff, nr, o.irep, st), "item reps"))) return rc;
     }
     if (p.path == kPathExact) {
         // k beyond the register shortlist: exhaustive float64 inside each list
@@ -539,6 +543,7 @@ int search_oneshot(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t
     a.xn = ix->xn;
     a.item_total = o.ioff + nr;
     a.item_queue = w.bf.counters + 2;
+    a.irep = o.irep;
     a.ioff = o.ioff;
     a.roff = o.roff;
     a.qlist = o.qlist;
@@ -591,6 +596,7 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
     w->roff = cv.take<int32_t>(nr + 1);
     w->ioff = cv.take<int32_t>(nr + 1);
     w->qlist = cv.take<int32_t>(m * nr);
+    w->irep = cv.take<int32_t>(m * nr / kWave + nr + 1);
 }
 
 int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
@@ -642,6 +648,7 @@ int search_exact_lowp(const rbc_index* ix, const BfPlan& p, const float* Q, int6
     a.xscale = qc.scale;
     a.item_total = w.ioff + nr;
     a.item_queue = w.bf.counters + 2;
+    a.irep = w.irep;
     a.ioff = w.ioff;
     a.roff = w.roff;
     a.qlist = w.qlist;
@@ -719,6 +726,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
         if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, isize, w.roff, w.ioff, w.qlist,
                                         st), "work list")))
             return rc;
+        if ((rc = check(launch_item_reps(w.ioff, nr, w.irep, st), "item reps"))) return rc;
         if (p.path == kPathLowp) {
             const rbc_index::Quant& qc = ix->quant[p.prec];
             uint32_t* ctr = (uint32_t*)w.bf.counters;
@@ -755,6 +763,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     a.xn = ix->xn;
     a.item_total = w.ioff + nr;
     a.item_queue = w.bf.counters + 2;
+    a.irep = w.irep;
     a.ioff = w.ioff;
     a.roff = w.roff;
     a.qlist = w.qlist;

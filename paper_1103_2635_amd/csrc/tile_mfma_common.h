@@ -237,12 +237,15 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
     const int g = lane >> 4;
     const int c16 = lane & 15;
     const int total = *a.item_total;
+    // The next item's ticket is taken while the current item is scanned, so
+    // the queue's latency is off the critical path.  The ticket is made
+    // wave-uniform (readfirstlane) so the loop control is scalar.
+    int ticket = 0;
+    if (lane == 0) ticket = atomicAdd(a.item_queue, 1);
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(a.item_queue, 1);
-        item = __shfl(item, 0);
+        const int item = __builtin_amdgcn_readfirstlane(__shfl(ticket, 0));
         if (item >= total) break;
-        const int r = item_rep(a, item);
+        const int r = a.irep ? __builtin_amdgcn_readfirstlane(a.irep[item]) : item_rep(a, item);
         const int q_begin = a.roff[r] + (item - a.ioff[r]) * kWave;
         const int q_end = a.roff[r + 1];
         typename P::QFrag qf[4][P::kBlocks];
@@ -258,6 +261,9 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         const int q = a.qlist[valid ? p : q_end - 1];
         TopC<C> top;
         if (a.tau) top.seed(a.tau[q]); else top.init();
+        // next ticket: issued after this item's metadata loads (memory
+        // counters retire in issue order), consumed at the next iteration
+        if (lane == 0) ticket = atomicAdd(a.item_queue, 1);
         scan_rows<P, C>(qf, a, a.list_off[r], a.list_off[r + 1], valid, top, tbuf_wave, lane);
         if (valid) {
             const int64_t pair =
