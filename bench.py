@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="also run the one-shot workload (2M x 128 clustered integer data) and the "
                          "4M x 128 brute force / exact RBC per precision (fp32, bf16, fp8)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also sweep the approximate variant's eps and the number of "
+                         "representatives n_r on the headline workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -235,6 +238,7 @@ def main():
 
     serving = run_serving(rbc, torch, dev) if args.serving else None
     configs = run_configs(rbc, torch, dev) if args.configs else None
+    sweep = run_sweeps(rbc, torch, dev, Xd, Qd, w, reps) if args.sweep else None
 
     line = {
         "metric": "exact k-NN queries/s (n=1M, d=64), RBC build+search vs BF, recall 1.0",
@@ -274,7 +278,70 @@ def main():
         line["serving"] = serving
     if configs:
         line["configs"] = configs
+    if sweep:
+        line["sweeps"] = sweep
     print(json.dumps(line))
+
+
+def run_sweeps(rbc, torch, dev, Xd, Qd, w, reps):
+    """On the headline workload (L2, k = 1):
+    - the approximate variant: prune_eps in {0, 0.1, 0.25, 0.5, 1, 2}: search
+      time, candidates, recall@1 against brute force and the mean rank of the
+      returned point (points strictly closer, counted among the 64 nearest);
+    - the number of representatives: n_r from 250 to 8,000 (uniform draws),
+      exact search: build and search time, candidates per query."""
+    import numpy as np
+
+    import datagen
+
+    sync = torch.cuda.synchronize
+    m = Qd.shape[0]
+    n = Xd.shape[0]
+    out = {}
+    bi, bd = rbc.bf_search(Qd, Xd, 64, "l2")
+    sync()
+    bd64 = bd.cpu().numpy()
+    bi1 = bi[:, 0].cpu().numpy()
+    ix = rbc.rbc_build(Xd, w.n_r, rep_idx=reps)
+    ws = torch.empty(rbc.rbc_search_workspace_size(ix, m, 1), dtype=torch.uint8, device=dev)
+    o = (torch.empty((m, 1), dtype=torch.int64, device=dev),
+         torch.empty((m, 1), dtype=torch.float32, device=dev))
+    eps_rows = []
+    for eps in (0.0, 0.1, 0.25, 0.5, 1.0, 2.0):
+        ms = _timed(lambda: rbc.rbc_search(ix, Qd, 1, out=o, workspace=ws, prune_eps=eps), 5, 2,
+                    sync)
+        st = rbc.new_stats()
+        rbc.rbc_search(ix, Qd, 1, out=o, workspace=ws, prune_eps=eps, stats=st)
+        sync()
+        ri = o[0][:, 0].cpu().numpy()
+        rd = o[1][:, 0].cpu().numpy()
+        rank = (bd64 < rd[:, None] * (1 - 1e-6)).sum(1)
+        eps_rows.append({"eps": eps, "search_ms": round(ms, 3), "qps": round(m / ms * 1e3, 1),
+                         "candidate_fraction": round(float(st.cpu().numpy()[rbc.STAT_CAND]) / (m * n), 4),
+                         "recall_at_1": round(float(np.mean((ri == bi1) | (rank == 0))), 4),
+                         "mean_rank": round(float(rank.mean()), 3), "max_rank_capped_64": int(rank.max())})
+    ix.free()
+    out["approximate_eps"] = eps_rows
+    nr_rows = []
+    for n_r in (250, 500, 1000, 2000, 4000, 8000):
+        rr = datagen.random_reps(n, n_r, seed=23)
+        b_ms = _timed(lambda: rbc.rbc_build(Xd, n_r, rep_idx=rr).free(), 2, 1, sync)
+        ix = rbc.rbc_build(Xd, n_r, rep_idx=rr)
+        ws = torch.empty(rbc.rbc_search_workspace_size(ix, m, 1), dtype=torch.uint8, device=dev)
+        s_ms = _timed(lambda: rbc.rbc_search(ix, Qd, 1, out=o, workspace=ws), 5, 2, sync)
+        st = rbc.new_stats()
+        rbc.rbc_search(ix, Qd, 1, out=o, workspace=ws, stats=st)
+        sync()
+        stn = st.cpu().numpy()
+        nr_rows.append({"n_r": n_r, "build_ms": round(b_ms, 3), "search_ms": round(s_ms, 3),
+                        "step_qps": round(m / (b_ms + s_ms) * 1e3, 1),
+                        "candidates_per_query": round(float(stn[rbc.STAT_CAND]) / m, 1),
+                        "lists_per_query": round(float(stn[rbc.STAT_LISTS]) / m, 1)})
+        ix.free()
+        del ws
+    out["n_r"] = nr_rows
+    out["workload"] = "sub8: n=1,000,000 d=64, m=10,000, l2, k=1"
+    return out
 
 
 MFMA_PEAK_TF = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}

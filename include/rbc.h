@@ -99,6 +99,13 @@ typedef struct rbc_search_opts {
                                the ranking tile, before re-scoring (not written for queries
                                re-ranked by the float32 cascade or the float64
                                fallback) */
+    float prune_eps;    /* rbc_search, exact mode: 0 = exact.  eps > 0 prunes with the
+                           bounds divided by (1 + eps) -- rule 1 at gamma_k / (1 + eps),
+                           rule 2 at (2 gamma_k + gamma_1) / (1 + eps) -- the approximate
+                           variant the paper mentions beside Sec. 5: the result is the exact
+                           k-NN among the points of the lists kept, not necessarily the
+                           exact k-NN of X.  Must be 0 for bf_search and one-shot indexes. */
+    int32_t reserved;   /* must be 0 */
 } rbc_search_opts;
 
 /* Index construction parameters. */

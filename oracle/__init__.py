@@ -51,11 +51,14 @@ def _load():
         lib.orc_rbc_build_exact.argtypes = [P, I64, I32, I32, P, I64, P, P, P, P]
         lib.orc_rbc_search_exact.argtypes = [P, I64, P, I64, I32, I32, P, I64, P, P, P, I32,
                                              I32, P, P, P, P, P]
+        lib.orc_rbc_search_approx.argtypes = [P, I64, P, I64, I32, I32, P, I64, P, P, P, I32,
+                                              I32, ctypes.c_double, P, P, P, P, P]
         lib.orc_rbc_build_oneshot.argtypes = [P, I64, I32, I32, P, I64, I64, P, P]
         lib.orc_rbc_search_oneshot.argtypes = [P, I64, P, I64, I32, I32, P, I64, I64, P, I32,
                                                P, P, P]
         for f in ("orc_rho_pairs", "orc_bf_knn", "orc_rank", "orc_rbc_build_exact",
-                  "orc_rbc_search_exact", "orc_rbc_build_oneshot", "orc_rbc_search_oneshot"):
+                  "orc_rbc_search_exact", "orc_rbc_search_approx", "orc_rbc_build_oneshot",
+                  "orc_rbc_search_oneshot"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -141,6 +144,28 @@ def rbc_search_exact(Q, X, index, k, metric="l2", strict=True, return_kept=False
         _p(Q), m, _p(X), X.shape[0], d, METRICS[metric], _p(reps), n_r, _p(index["psi"]),
         _p(index["list_off"]), _p(index["list_ids"]), k, 1 if strict else 0, _p(idx), _p(dist),
         _p(ncand), _p(nkept), _p(kept)), "rbc_search_exact")
+    if return_kept:
+        return idx, dist, ncand, nkept, kept.astype(bool)
+    return idx, dist, ncand, nkept
+
+
+def rbc_search_approx(Q, X, index, k, eps, metric="l2", return_kept=False):
+    """The approximate variant beside Sec. 5: both pruning bounds divided by
+    (1 + eps); the answer is BF over the kept lists.  (idx, dist, ncand,
+    nkept[, kept mask])."""
+    Q, X = _f32(Q), _f32(X)
+    m, d = Q.shape
+    reps = index["rep_idx"]
+    n_r = reps.shape[0]
+    idx = np.empty((m, k), np.int64)
+    dist = np.empty((m, k), np.float64)
+    ncand = np.empty(m, np.int64)
+    nkept = np.empty(m, np.int32)
+    kept = np.empty((m, n_r), np.uint8) if return_kept else None
+    _check(_load().orc_rbc_search_approx(
+        _p(Q), m, _p(X), X.shape[0], d, METRICS[metric], _p(reps), n_r, _p(index["psi"]),
+        _p(index["list_off"]), _p(index["list_ids"]), k, 1, float(eps), _p(idx), _p(dist),
+        _p(ncand), _p(nkept), _p(kept)), "rbc_search_approx")
     if return_kept:
         return idx, dist, ncand, nkept, kept.astype(bool)
     return idx, dist, ncand, nkept

@@ -253,6 +253,21 @@ int orc_rbc_build_exact(const float* X, int64_t n, int32_t d, int32_t metric,
  * of candidate points scanned; the number of lists kept; optionally the m x n_r
  * keep mask.
  */
+/*
+ * The approximate variant the paper mentions beside Sec. 5 (prune harder
+ * than the exact rules allow): both rules compare against their bounds
+ * divided by (1 + eps), i.e. rule 1 prunes r when rho(q,r) - psi_r >
+ * gamma_k / (1 + eps) and rule 2 when rho(q,r) > (2 gamma_k + gamma_1) /
+ * (1 + eps).  The result is BF(q, X[union of the kept lists]); eps = 0 is the
+ * exact search above.
+ */
+int orc_rbc_search_approx(const float* Q, int64_t m, const float* X, int64_t n, int32_t d,
+                          int32_t metric, const int64_t* rep_idx, int64_t n_r,
+                          const double* psi, const int64_t* list_off,
+                          const int64_t* list_ids, int32_t k, int32_t strict, double eps,
+                          int64_t* out_idx, double* out_dist, int64_t* out_ncand,
+                          int32_t* out_nkept, uint8_t* out_kept);
+
 int orc_rbc_search_exact(const float* Q, int64_t m, const float* X, int64_t n, int32_t d,
                          int32_t metric, const int64_t* rep_idx, int64_t n_r,
                          const double* psi, const int64_t* list_off,
@@ -260,8 +275,21 @@ int orc_rbc_search_exact(const float* Q, int64_t m, const float* X, int64_t n, i
                          int64_t* out_idx, double* out_dist, int64_t* out_ncand,
                          int32_t* out_nkept, uint8_t* out_kept)
 {
+    return orc_rbc_search_approx(Q, m, X, n, d, metric, rep_idx, n_r, psi, list_off, list_ids,
+                                 k, strict, 0.0, out_idx, out_dist, out_ncand, out_nkept,
+                                 out_kept);
+}
+
+int orc_rbc_search_approx(const float* Q, int64_t m, const float* X, int64_t n, int32_t d,
+                          int32_t metric, const int64_t* rep_idx, int64_t n_r,
+                          const double* psi, const int64_t* list_off,
+                          const int64_t* list_ids, int32_t k, int32_t strict, double eps,
+                          int64_t* out_idx, double* out_dist, int64_t* out_ncand,
+                          int32_t* out_nkept, uint8_t* out_kept)
+{
     int64_t i;
-    if (k < 1 || k > n || d < 1) return -1;
+    const double shrink = 1.0 / (1.0 + eps);
+    if (k < 1 || k > n || d < 1 || !(eps >= 0.0)) return -1;
 #pragma omp parallel for schedule(dynamic, 1)
     for (i = 0; i < m; ++i) {
         const float* q = Q + i * (int64_t)d;
@@ -294,8 +322,8 @@ int orc_rbc_search_exact(const float* Q, int64_t m, const float* X, int64_t n, i
 
         /* step 2: pruning rules (1) and (2) */
         for (r = 0; r < n_r; ++r) {
-            int prune1 = strict ? (dr[r] - psi[r] > gk) : (dr[r] >= gk + psi[r]);
-            int prune2 = dr[r] > 2.0 * gk + g1;
+            int prune1 = strict ? (dr[r] - psi[r] > gk * shrink) : (dr[r] >= gk * shrink + psi[r]);
+            int prune2 = dr[r] > (2.0 * gk + g1) * shrink;
             int keep = !(prune1 || prune2);
             if (out_kept) out_kept[i * n_r + r] = (uint8_t)keep;
             if (keep) {
@@ -308,8 +336,8 @@ int orc_rbc_search_exact(const float* Q, int64_t m, const float* X, int64_t n, i
         cand = (int64_t*)malloc((size_t)(ncand > 0 ? ncand : 1) * sizeof(int64_t));
         j = 0;
         for (r = 0; r < n_r; ++r) {
-            int prune1 = strict ? (dr[r] - psi[r] > gk) : (dr[r] >= gk + psi[r]);
-            int prune2 = dr[r] > 2.0 * gk + g1;
+            int prune1 = strict ? (dr[r] - psi[r] > gk * shrink) : (dr[r] >= gk * shrink + psi[r]);
+            int prune2 = dr[r] > (2.0 * gk + g1) * shrink;
             if (!(prune1 || prune2)) {
                 int64_t t;
                 for (t = list_off[r]; t < list_off[r + 1]; ++t) cand[j++] = list_ids[t];

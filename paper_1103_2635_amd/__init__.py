@@ -34,7 +34,8 @@ _SZ = ctypes.c_size_t
 
 class SearchOpts(ctypes.Structure):
     _fields_ = [("precision", _I32), ("shortlist", _I32), ("splits", _I32), ("flags", _I32),
-                ("dev_stats", _P), ("dev_approx_dist", _P)]
+                ("dev_stats", _P), ("dev_approx_dist", _P), ("prune_eps", ctypes.c_float),
+                ("reserved", _I32)]
 
 
 class BuildParams(ctypes.Structure):
@@ -100,12 +101,13 @@ def _mat(t, name):
     return t
 
 
-def _opts(precision="fp32", shortlist=0, splits=0, stats=None, approx_dist=None):
+def _opts(precision="fp32", shortlist=0, splits=0, stats=None, approx_dist=None, prune_eps=0.0):
     o = SearchOpts()
     o.precision = _PRECS[precision]
     o.shortlist = int(shortlist)
     o.splits = int(splits)
     o.flags = 0
+    o.prune_eps = float(prune_eps)
     if stats is not None:
         if stats.dtype != torch.int64 or not stats.is_cuda or stats.numel() < STATS_LEN:
             raise ValueError("stats must be a GPU int64 tensor of %d counters" % STATS_LEN)

@@ -574,7 +574,8 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
                                                     int32_t nr, int32_t k, int32_t c,
                                                     double delta, const double* psi,
                                                     const int32_t* list_off, int32_t* lrank,
-                                                    int32_t* nkept, float* gcup, int64_t* stats) {
+                                                    int32_t* nkept, float* gcup, int64_t* stats,
+                                                    double shrink) {
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= m) return;
@@ -585,8 +586,10 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
     const float gk = k <= nr ? __uint_as_float(pk) : RBC_INF;
     const float gc = c <= nr ? __uint_as_float(pc) : RBC_INF;
     const double g1_up = (double)g1 * (1.0 + delta);
+    // shrink < 1: the approximate variant (bounds divided by 1 + eps)
     const double gk_up = (double)gk * (1.0 + delta);
-    const double bound2 = 2.0 * gk_up + g1_up;
+    const double bound2 = (2.0 * gk_up + g1_up) * shrink;
+    const double bound1 = gk_up * shrink;
     int running = 0;
     int64_t ncand = 0;
     for (int base = 0; base < nr; base += 64) {
@@ -595,7 +598,7 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
         if (r < nr) {
             const double lo = (double)row[r] * (1.0 - delta);
             const double ps = psi[r] * (1.0 + 1e-15);
-            kept = !((lo - ps > gk_up) || (lo > bound2));
+            kept = !((lo - ps > bound1) || (lo > bound2));
         }
         const uint64_t bits = __ballot(kept);
         const uint64_t below = lane ? (bits & (~0ull >> (64 - lane))) : 0ull;
@@ -621,17 +624,18 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
 
 hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
                         double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
-                        int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st) {
+                        int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st,
+                        double shrink) {
     const dim3 grid((m + 3) / 4);
     if (nr <= 1024)
         hipLaunchKernelGGL(prune_kernel<16>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
-                           psi, list_off, lrank, nkept, gcup, stats);
+                           psi, list_off, lrank, nkept, gcup, stats, shrink);
     else if (nr <= 2048)
         hipLaunchKernelGGL(prune_kernel<32>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
-                           psi, list_off, lrank, nkept, gcup, stats);
+                           psi, list_off, lrank, nkept, gcup, stats, shrink);
     else
         hipLaunchKernelGGL(prune_kernel<0>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
-                           psi, list_off, lrank, nkept, gcup, stats);
+                           psi, list_off, lrank, nkept, gcup, stats, shrink);
     return hipGetLastError();
 }
 

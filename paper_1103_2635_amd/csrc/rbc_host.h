@@ -68,6 +68,7 @@ struct BfPlan {
     int ks32;          // its 16-feature slabs
     int64_t ldc;       // row length of the compacted query copies (d rounded up to 4)
     int32_t casc_blocks;  // its workgroups
+    double prune_eps;     // exact RBC search: pruning bounds divided by (1 + eps)
 };
 
 struct BfWork {

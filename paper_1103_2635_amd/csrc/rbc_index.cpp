@@ -609,6 +609,8 @@ int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
     }
     if (ix->mode == RBC_ONESHOT && k > ix->s)
         return set_err(RBC_EINVAL, "one-shot search needs k <= s (%lld)", (long long)ix->s);
+    if (ix->mode == RBC_ONESHOT && opts && opts->prune_eps != 0.0f)
+        return set_err(RBC_EINVAL, "prune_eps applies to exact indexes");
     if (ix->mode == RBC_EXACT && (int64_t)m * ix->n_r >= ((int64_t)1 << 31))
         return set_err(RBC_EUNSUPPORTED, "m * n_r >= 2^31: split the query batch");
     int rc = make_bf_plan(m > 0 ? m : 1, ix->rows, ix->d, ldq, ix->ld, ix->metric, k, opts, p);
@@ -710,7 +712,8 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     {
         KernelTimer kt("prune", st);
         if ((rc = check(launch_prune(w.DR, ldd, (int32_t)m, nr, k, p.c, delta, ix->psi,
-                                     ix->list_off, w.lrank, w.npairs, w.gcup, stats, st),
+                                     ix->list_off, w.lrank, w.npairs, w.gcup, stats, st,
+                                     1.0 / (1.0 + p.prune_eps)),
                         "prune")))
             return rc;
         if ((rc = check(launch_keep_transpose(w.lrank, (int32_t)m, nr, w.keep_rq, st), "keep")))

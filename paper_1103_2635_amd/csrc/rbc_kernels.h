@@ -40,7 +40,8 @@ hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, c
                            hipStream_t st);
 hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
                         double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
-                        int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st);
+                        int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st,
+                        double shrink = 1.0);
 hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
                                  hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.

@@ -48,6 +48,48 @@ def test_worked_exact_search(orc, metric):
         np.testing.assert_allclose(dist[0], c["dist"], rtol=1e-6)
 
 
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+def test_worked_approx_search(orc, metric):
+    """The approximate variant (bounds divided by 1 + eps) on the hand-worked
+    1-D cases: eps = 0.2 prunes the list that holds the true neighbour."""
+    g = _golden()["approx_search_1d"]
+    X = _col(g["X"])
+    ix = orc.rbc_build_exact(X, g["rep_idx"], metric)
+    for c in g["cases"]:
+        idx, dist, ncand, nkept, kept = orc.rbc_search_approx(_col([c["q"]]), X, ix, c["k"],
+                                                              c["eps"], metric, return_kept=True)
+        assert kept[0].tolist() == c["kept"], c
+        assert idx[0].tolist() == c["idx"], c
+        np.testing.assert_allclose(dist[0], c["dist"], rtol=1e-6)
+
+
+def test_approx_search_properties(orc):
+    """eps = 0 is the exact search; the kept lists shrink as eps grows; every
+    answer is the exact k-NN of the kept lists, never closer than BF."""
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((3000, 8)).astype(np.float32)
+    Q = rng.standard_normal((60, 8)).astype(np.float32)
+    reps = np.sort(rng.choice(3000, 55, replace=False))
+    ix = orc.rbc_build_exact(X, reps, "l2")
+    ref = orc.bf_knn(Q, X, 3, "l2")
+    e_idx, e_dist, _, _ = orc.rbc_search_exact(Q, X, ix, 3, "l2")
+    a_idx, a_dist, _, _ = orc.rbc_search_approx(Q, X, ix, 3, 0.0, "l2")
+    assert np.array_equal(a_idx, e_idx) and np.array_equal(a_dist, e_dist)
+    prev = None
+    for eps in (0.0, 0.1, 0.5, 2.0):
+        idx, dist, ncand, nkept, kept = orc.rbc_search_approx(Q, X, ix, 3, eps, "l2",
+                                                              return_kept=True)
+        if prev is not None:
+            assert not (kept & ~prev).any()          # monotone in eps
+        prev = kept
+        assert (dist >= ref[1] - 1e-12).all()        # never better than brute force
+        for i in range(Q.shape[0]):                  # exact k-NN of the kept lists
+            rows = np.concatenate([ix["list_ids"][ix["list_off"][r]:ix["list_off"][r + 1]]
+                                   for r in np.nonzero(kept[i])[0]])
+            sub_i, sub_d = orc.bf_knn(Q[i:i + 1], X[rows], 3, "l2")
+            np.testing.assert_allclose(dist[i], sub_d[0], rtol=1e-12)
+
+
 def test_worked_psi_zero_boundary(orc):
     """Strict pruning keeps the nearest representative that owns only itself;
     the literal non-strict rule empties the candidate set (planted mistake)."""

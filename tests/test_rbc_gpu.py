@@ -186,3 +186,38 @@ def test_headline_full_size_sampled(rbc, orc, metric, k):
     sample = np.random.default_rng(10 + k).choice(Q.shape[0], 48, replace=False)
     assert_knn_parity(idx[sample], dist[sample], Q[sample], X, k, metric, orc)
     print("candidates/query %.0f lists/query %.1f fallbacks %d" % (st[4] / 1e4, st[3] / 1e4, st[0]))
+
+
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+def test_approximate_search(rbc, orc, metric):
+    """prune_eps (the approximate variant beside Sec. 5): eps = 0 is the exact
+    search; for eps > 0 the GPU keeps a superset of the oracle's lists (its
+    margins only widen), so each returned distance lies between brute force
+    and the oracle's approximate answer, and the kept-list count covers the
+    oracle's."""
+    import torch
+
+    X, Q = datagen.database("sub8", 50000), datagen.queries("sub8", 400)
+    reps = datagen.representatives("sub8", 50000, 224)
+    ix = rbc.rbc_build(_dev(X), 224, metric=metric, rep_idx=reps)
+    oix = orc.rbc_build_exact(X, reps, metric)
+    bf_i, bf_d = orc.bf_knn(Q, X, 10, metric)
+    e_idx, e_dist, _ = _search(rbc, ix, Q, 10)
+    z_idx, z_dist, _ = _search(rbc, ix, Q, 10, prune_eps=0.0)
+    assert np.array_equal(e_idx, z_idx) and np.array_equal(e_dist, z_dist)
+    for eps in (0.25, 1.0):
+        idx, dist, st = _search(rbc, ix, Q, 10, prune_eps=eps)
+        o_idx, o_dist, o_ncand, o_nkept = orc.rbc_search_approx(Q, X, oix, 10, eps, metric)
+        rho = orc.rho_pairs(np.repeat(Q, 10, 0), X[idx.reshape(-1)], metric).reshape(idx.shape)
+        np.testing.assert_allclose(dist, rho, rtol=1e-5)                  # true distances
+        assert (rho >= bf_d * (1 - 1e-6)).all()
+        assert (rho <= o_dist * (1 + 1e-6) + 1e-12).all()
+        assert st[3] >= o_nkept.sum()
+        recall = np.mean(idx[:, 0] == bf_i[:, 0])
+        print("%s eps=%.2f lists %d (oracle %d) recall@1 %.3f" % (metric, eps, st[3],
+                                                                o_nkept.sum(), recall))
+    with pytest.raises(rbc.RbcError):
+        rbc.bf_search(_dev(Q), _dev(X), 1, metric, prune_eps=0.5)
+    with pytest.raises(rbc.RbcError):
+        _search(rbc, ix, Q, 1, prune_eps=-1.0)
+    ix.free()
