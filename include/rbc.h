@@ -191,6 +191,44 @@ int rbc_search(const rbc_index* index, const float* Q, int64_t m, int64_t ldq, i
                void* workspace, size_t ws_bytes, void* hip_stream);
 
 /*
+ * Range search over an exact index (the eps-range extension named in the
+ * introduction of Sec. 5): every database point x with rho(q, x) <= radius,
+ * decided in float64 exactly as a direct float64 evaluation of rho decides
+ * it (float32 distances settle only the points clearly inside or outside).
+ * Same stage 1 as rbc_search; list L_r is skipped when rho(q, r) - psi_r >
+ * radius (triangle inequality, the bound widened by the float32 error of
+ * rho(q, r)); the kept lists are scanned with the vector tile.  The output
+ * size depends on the data, so the search takes two calls on the same
+ * index, Q and radius:
+ *   rbc_range_count   writes offsets[m + 1] (device int64): offsets[0] = 0,
+ *                     offsets[i + 1] - offsets[i] = the number of points
+ *                     within radius of query i.  Asynchronous on the stream.
+ *   rbc_range_search  given those offsets, writes the points of query i to
+ *                     out_idx / out_dist[offsets[i] .. offsets[i + 1]) (device
+ *                     int64 row ids of X and float32 roundings of the float64
+ *                     distances) in ascending (float32 distance, id) order.
+ *                     The call synchronises the stream: it checks that every
+ *                     query found exactly as many points as its segment holds
+ *                     (RBC_EINVAL when the offsets do not belong to this
+ *                     index, Q and radius; points beyond a segment are then
+ *                     dropped, never written outside it, and the segments
+ *                     that do not match are left unsorted).
+ * Q: m x d (ldq) device float32; radius finite and >= 0; `workspace` of at
+ * least rbc_range_workspace_size() bytes, used by one call at a time.
+ * Segments longer than 8192 points are sorted in global memory (slower).
+ * Errors: RBC_EINVAL (bad sizes, NULL pointers, radius negative or not
+ * finite, mismatched offsets); RBC_EUNSUPPORTED for one-shot indexes, d > 128
+ * or m * n_r >= 2^31; RBC_EWORKSPACE.
+ */
+int rbc_range_workspace_size(const rbc_index* index, int64_t m, int64_t ldq, size_t* bytes);
+int rbc_range_count(const rbc_index* index, const float* Q, int64_t m, int64_t ldq,
+                    double radius, int64_t* offsets, void* workspace, size_t ws_bytes,
+                    void* hip_stream);
+int rbc_range_search(const rbc_index* index, const float* Q, int64_t m, int64_t ldq,
+                     double radius, const int64_t* offsets, int64_t* out_idx, float* out_dist,
+                     void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
  * rbc_index_info -- sizes of a built index (any output pointer may be NULL).
  */
 int rbc_index_info(const rbc_index* index, int64_t* n, int32_t* d, int64_t* n_r,
@@ -231,7 +269,8 @@ void rbc_free(rbc_index* index);
  * of the kernels called `name`: "tile" (BF distance tile), "tile_items"
  * (RBC stage 2), "finalize", "fallback", "stage1", "prune", "worklist",
  * "quantize", "cascade" (the float32 re-ranking of low-precision queries
- * whose certificate failed), "oneshot_tile", "oneshot_select".
+ * whose certificate failed), "oneshot_tile", "oneshot_select", "range_tile"
+ * (both range passes), "range_sort".
  */
 int rbc_timer_enable(int on);
 int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);

@@ -53,11 +53,13 @@ def _load():
                                              I32, P, P, P, P, P]
         lib.orc_rbc_search_approx.argtypes = [P, I64, P, I64, I32, I32, P, I64, P, P, P, I32,
                                               I32, ctypes.c_double, P, P, P, P, P]
+        lib.orc_range_bf.argtypes = [P, I64, P, I64, I32, I32, ctypes.c_double, P, P, P]
         lib.orc_rbc_build_oneshot.argtypes = [P, I64, I32, I32, P, I64, I64, P, P]
         lib.orc_rbc_search_oneshot.argtypes = [P, I64, P, I64, I32, I32, P, I64, I64, P, I32,
                                                P, P, P]
         for f in ("orc_rho_pairs", "orc_bf_knn", "orc_rank", "orc_rbc_build_exact",
-                  "orc_rbc_search_exact", "orc_rbc_search_approx", "orc_rbc_build_oneshot",
+                  "orc_rbc_search_exact", "orc_rbc_search_approx", "orc_range_bf",
+                  "orc_rbc_build_oneshot",
                   "orc_rbc_search_oneshot"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -169,6 +171,23 @@ def rbc_search_approx(Q, X, index, k, eps, metric="l2", return_kept=False):
     if return_kept:
         return idx, dist, ncand, nkept, kept.astype(bool)
     return idx, dist, ncand, nkept
+
+
+def range_bf(Q, X, radius, metric="l2"):
+    """Range search by its definition: (offsets[m+1], ids, distances) with
+    query i's points at offsets[i] .. offsets[i+1], in (distance, id) order."""
+    Q, X = _f32(Q), _f32(X)
+    m, d = Q.shape
+    cnt = np.zeros(m + 1, np.int64)
+    _check(_load().orc_range_bf(_p(Q), m, _p(X), X.shape[0], d, METRICS[metric], float(radius),
+                                _p(cnt), None, None), "range_bf count")
+    off = np.zeros(m + 1, np.int64)
+    off[1:] = np.cumsum(cnt[:m])
+    idx = np.empty(max(int(off[-1]), 1), np.int64)
+    dist = np.empty(max(int(off[-1]), 1), np.float64)
+    _check(_load().orc_range_bf(_p(Q), m, _p(X), X.shape[0], d, METRICS[metric], float(radius),
+                                _p(off), _p(idx), _p(dist)), "range_bf fill")
+    return off, idx[:off[-1]], dist[:off[-1]]
 
 
 def rbc_build_oneshot(X, rep_idx, s, metric="l2"):

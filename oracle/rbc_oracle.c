@@ -179,6 +179,57 @@ int orc_bf_knn(const float* Q, int64_t m, const float* X, int64_t n, int32_t d,
     return 0;
 }
 
+/*
+ * Range search (the eps-range form of the problem Sec. 5 mentions beside
+ * k-NN): for every query q, all database points x with rho(q, x) <= radius, in
+ * (distance, index) order.  Called twice: with out_idx NULL it writes the
+ * per-query counts to off[0 .. m) (the caller turns them into offsets); then
+ * with off[i] .. off[i+1] the output ranges it fills them.
+ */
+int orc_range_bf(const float* Q, int64_t m, const float* X, int64_t n, int32_t d,
+                 int32_t metric, double radius, int64_t* off, int64_t* out_idx,
+                 double* out_dist)
+{
+    int64_t i;
+    if (d < 1 || n < 0 || m < 0 || !(radius >= 0.0)) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (i = 0; i < m; ++i) {
+        const float* q = Q + i * (int64_t)d;
+        int64_t j, c = 0;
+        if (!out_idx) {
+            for (j = 0; j < n; ++j)
+                if (rho(q, X + j * (int64_t)d, d, metric) <= radius) ++c;
+            off[i] = c;
+            continue;
+        }
+        {
+            int64_t base = off[i], cnt = off[i + 1] - off[i], a, b;
+            for (j = 0; j < n; ++j) {
+                double r = rho(q, X + j * (int64_t)d, d, metric);
+                if (r <= radius) {
+                    out_idx[base + c] = j;
+                    out_dist[base + c] = r;
+                    ++c;
+                }
+            }
+            /* insertion sort of the (short) result list by (distance, index) */
+            for (a = 1; a < cnt; ++a) {
+                double dv = out_dist[base + a];
+                int64_t iv = out_idx[base + a];
+                b = a - 1;
+                while (b >= 0 && before(dv, iv, out_dist[base + b], out_idx[base + b])) {
+                    out_dist[base + b + 1] = out_dist[base + b];
+                    out_idx[base + b + 1] = out_idx[base + b];
+                    --b;
+                }
+                out_dist[base + b + 1] = dv;
+                out_idx[base + b + 1] = iv;
+            }
+        }
+    }
+    return 0;
+}
+
 /* Number of database points strictly closer to q than the given distance: the
  * rank error measure of the one-shot experiments (Sec. 7). */
 int orc_rank(const float* Q, int64_t m, const float* X, int64_t n, int32_t d,

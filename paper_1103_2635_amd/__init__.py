@@ -68,6 +68,10 @@ def lib():
         L.rbc_build.argtypes = [_P, _I64, _I64, _I32, _P, _P, ctypes.POINTER(_P)]
         L.rbc_search_workspace_size.argtypes = [_P, _I64, _I64, _I32, _P, ctypes.POINTER(_SZ)]
         L.rbc_search.argtypes = [_P, _P, _I64, _I64, _I32, _P, _P, _P, _P, _SZ, _P]
+        L.rbc_range_workspace_size.argtypes = [_P, _I64, _I64, ctypes.POINTER(_SZ)]
+        L.rbc_range_count.argtypes = [_P, _P, _I64, _I64, ctypes.c_double, _P, _P, _SZ, _P]
+        L.rbc_range_search.argtypes = [_P, _P, _I64, _I64, ctypes.c_double, _P, _P, _P, _P, _SZ,
+                                       _P]
         L.rbc_index_info.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_I64), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_I32), ctypes.POINTER(_SZ)]
@@ -271,6 +275,49 @@ def rbc_search(index, Q, k, out=None, workspace=None, **kw):
                             idx.data_ptr(), dist.data_ptr(), workspace.data_ptr(),
                             workspace.numel(), _stream_ptr(Q)))
     return idx, dist
+
+
+def rbc_range_workspace_size(index, m, ldq=None):
+    sz = _SZ()
+    _check(lib().rbc_range_workspace_size(index.handle, m, ldq or index.info()["d"],
+                                          ctypes.byref(sz)))
+    return sz.value
+
+
+def rbc_range_count(index, Q, radius, offsets=None, workspace=None):
+    """Offsets (device int64 [m + 1]) of every query's points within radius."""
+    _mat(Q, "Q")
+    m = Q.shape[0]
+    sz = _SZ()
+    _check(lib().rbc_range_workspace_size(index.handle, m, Q.stride(0), ctypes.byref(sz)))
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=Q.device)
+    if offsets is None:
+        offsets = torch.empty(m + 1, dtype=torch.int64, device=Q.device)
+    _check(lib().rbc_range_count(index.handle, Q.data_ptr(), m, Q.stride(0), float(radius),
+                                 offsets.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                 _stream_ptr(Q)))
+    return offsets
+
+
+def rbc_range_search(index, Q, radius, workspace=None):
+    """All points within radius of each query: (offsets int64 [m + 1], idx
+    int64 [total], dist float32 [total]); the points of query i are
+    idx[offsets[i]:offsets[i + 1]] in ascending (distance, id) order."""
+    _mat(Q, "Q")
+    m = Q.shape[0]
+    sz = _SZ()
+    _check(lib().rbc_range_workspace_size(index.handle, m, Q.stride(0), ctypes.byref(sz)))
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=Q.device)
+    off = rbc_range_count(index, Q, radius, workspace=workspace)
+    total = int(off[-1].item()) if m > 0 else 0
+    idx = torch.empty(max(total, 1), dtype=torch.int64, device=Q.device)
+    dist = torch.empty(max(total, 1), dtype=torch.float32, device=Q.device)
+    _check(lib().rbc_range_search(index.handle, Q.data_ptr(), m, Q.stride(0), float(radius),
+                                  off.data_ptr(), idx.data_ptr(), dist.data_ptr(),
+                                  workspace.data_ptr(), workspace.numel(), _stream_ptr(Q)))
+    return off, idx[:total], dist[:total]
 
 
 def timer_enable(on=True):

@@ -711,6 +711,150 @@ hipError_t launch_seg_sort(const int32_t* off, int32_t nseg, int32_t* vals, cons
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------- range search
+// Pruning for a range query (radius eps): a point x of L_r has rho(q, x) >=
+// rho(q, r) - rho(x, r) >= rho(q, r) - psi_r, so L_r can hold a point within
+// eps only when rho(q, r) - psi_r <= eps; applied to the lower bound of the
+// stored fp32 rho(q, r).  One wavefront per query; lrank as for k-NN pruning.
+__global__ __launch_bounds__(256) void prune_range_kernel(const float* DR, int64_t ldd, int32_t m,
+                                                          int32_t nr, double delta,
+                                                          const double* psi, double radius,
+                                                          int32_t* lrank, int32_t* nkept,
+                                                          int64_t* stats) {
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= m) return;
+    const float* row = DR + (int64_t)q * ldd;
+    int running = 0;
+    for (int base = 0; base < nr; base += 64) {
+        const int r = base + lane;
+        bool kept = false;
+        if (r < nr) {
+            // lower bound of rho(q, r) from the fp32 value; the float64
+            // difference is given a relative 1e-12 of slack (NaN keeps the list)
+            const double lo = (double)row[r] * (1.0 - delta), pr = psi[r];
+            kept = !(lo - pr > radius + 1e-12 * (lo + pr + radius));
+        }
+        const uint64_t bits = __ballot(kept);
+        const uint64_t below = lane ? (bits & (~0ull >> (64 - lane))) : 0ull;
+        if (r < nr) lrank[(int64_t)q * nr + r] = kept ? running + __popcll(below) : -1;
+        running += __popcll(bits);
+    }
+    if (lane == 0) {
+        nkept[q] = running;
+        if (stats) atomicAdd((unsigned long long*)&stats[3], (unsigned long long)running);
+    }
+}
+
+hipError_t launch_prune_range(const float* DR, int64_t ldd, int32_t m, int32_t nr, double delta,
+                              const double* psi, double radius, int32_t* lrank, int32_t* nkept,
+                              int64_t* stats, hipStream_t st) {
+    hipLaunchKernelGGL(prune_range_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, ldd, m, nr,
+                       delta, psi, radius, lrank, nkept, stats);
+    return hipGetLastError();
+}
+
+// off[0] = 0, off[i + 1] = off[i] + cnt[i] (int64), one workgroup.
+__global__ __launch_bounds__(1024) void offsets64_kernel(const int32_t* cnt, int64_t m,
+                                                         int64_t* off) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (m + 1023) / 1024;
+    const int64_t b = t * per, e = b + per < m ? b + per : m;
+    int64_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int step = 1; step < 1024; step <<= 1) {
+        const int64_t v = t >= step ? part[t - step] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;  // exclusive
+    for (int64_t i = b; i < e; ++i) {
+        off[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) off[m] = part[1023];
+}
+
+hipError_t launch_offsets64(const int32_t* cnt, int64_t m, int64_t* off, hipStream_t st) {
+    hipLaunchKernelGGL(offsets64_kernel, dim3(1), dim3(1024), 0, st, cnt, m, off);
+    return hipGetLastError();
+}
+
+// Each segment off[s] .. off[s + 1] of (dist, idx) pairs sorted by (dist,
+// idx) (with cnt: only segments whose length equals cnt[s]; the others are
+// counted in *bad and left as they are): keys (dist bits << 32 | idx) with dist >= 0 and 0 <= idx < 2^31.  A
+// bitonic network in the form that needs no direction flags (a "flip" step
+// then half-cleaners, all ascending), so a non-power-of-two length just skips
+// the comparisons with partners beyond the end (virtual +inf there never
+// moves).  Segments up to kSegCap run in LDS, longer ones in place in global
+// memory (same network, one workgroup).
+__global__ __launch_bounds__(1024) void seg_sort_pairs_kernel(const int64_t* off, int64_t* idx,
+                                                              float* dist, const int32_t* cnt,
+                                                              int32_t* bad) {
+    __shared__ uint64_t key[kSegCap];
+    const int64_t b = off[blockIdx.x];
+    const int64_t len = off[blockIdx.x + 1] - b;
+    if (cnt && cnt[blockIdx.x] != len) {  // segment not filled exactly: left unsorted
+        if (threadIdx.x == 0) atomicAdd(bad, 1);
+        return;
+    }
+    if (len <= 1) return;
+    const bool lds = len <= kSegCap;
+    int64_t size = 1;
+    while (size < len) size <<= 1;
+    auto get = [&](int64_t i) -> uint64_t {
+        return ((uint64_t)__float_as_uint(dist[b + i]) << 32) | (uint32_t)idx[b + i];
+    };
+    if (lds) {
+        for (int64_t i = threadIdx.x; i < len; i += blockDim.x) key[i] = get(i);
+        __syncthreads();
+    }
+    for (int64_t kk = 2; kk <= size; kk <<= 1) {
+        for (int64_t j = kk >> 1; j > 0; j >>= 1) {
+            for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+                // first step of a stage compares mirrored partners, later ones i ^ j
+                const int64_t p = j == (kk >> 1) ? (i ^ (kk - 1)) : (i ^ j);
+                if (p > i && p < len) {
+                    if (lds) {
+                        const uint64_t x = key[i], y = key[p];
+                        if (x > y) {
+                            key[i] = y;
+                            key[p] = x;
+                        }
+                    } else {
+                        const uint64_t x = get(i), y = get(p);
+                        if (x > y) {
+                            dist[b + i] = __uint_as_float((uint32_t)(y >> 32));
+                            idx[b + i] = (int64_t)(uint32_t)y;
+                            dist[b + p] = __uint_as_float((uint32_t)(x >> 32));
+                            idx[b + p] = (int64_t)(uint32_t)x;
+                        }
+                    }
+                }
+            }
+            if (!lds) __threadfence_block();
+            __syncthreads();
+        }
+    }
+    if (lds)
+        for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+            dist[b + i] = __uint_as_float((uint32_t)(key[i] >> 32));
+            idx[b + i] = (int64_t)(uint32_t)key[i];
+        }
+}
+
+hipError_t launch_seg_sort_pairs(const int64_t* off, int64_t nseg, int64_t* idx, float* dist,
+                                 const int32_t* cnt, int32_t* bad, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(seg_sort_pairs_kernel, dim3((unsigned)nseg), dim3(1024), 0, st, off, idx,
+                       dist, cnt, bad);
+    return hipGetLastError();
+}
+
 // keep_rq[r][q] = (lrank[q][r] >= 0), through 64 x 64 LDS tiles so that both
 // the reads and the writes are contiguous.
 __global__ __launch_bounds__(256) void keep_transpose_kernel(const int32_t* lrank, int32_t m,

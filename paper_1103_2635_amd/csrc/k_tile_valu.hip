@@ -167,6 +167,101 @@ __global__ __launch_bounds__(256, 2) void tile_valu_all(TileArgs a) {
     }
 }
 
+// Range search on the vector ALUs: persistent workgroups take (representative,
+// 256-query chunk) items; every lane scores its query against the list's rows
+// (staged 32 at a time in LDS) in fp32 direct form, whose relative error is
+// below delta = 2 (d + 2) u for the l2 square and the l1 sum alike.  A row is
+// inside when s (1 + delta) <= bound, outside when s (1 - delta) > bound
+// (bound = radius^2 for l2, radius for l1); in between, the float64 distance
+// in the fixed order of rho_fp64 decides, so membership is that of the
+// float64 definition.
+template <int METRIC, int KS>
+__global__ __launch_bounds__(256, 2) void tile_valu_range(TileArgs a) {
+    constexpr int F4 = 4 * KS;
+    __shared__ f4 xs[kRowsValu * F4];
+    __shared__ int s_item;
+    const int total = *a.item_total;
+    const double delta = 2.0 * (a.d + 2) * 5.9604644775390625e-8;
+    // sv, the fp32 sum, lies within a relative delta of the exact sum, plus an
+    // absolute d * 2^-149 for terms that underflow; rows clearly inside
+    // (count pass) or clearly outside skip the float64 distance, the rest are
+    // decided on it, as the reference computation decides them
+    const double bound = METRIC == 0 ? a.range_radius * a.range_radius : a.range_radius;
+    const double tiny = a.d * 1e-44;
+    const double b_in = bound * (1.0 - 2.0 * delta) - tiny;
+    const double b_out = bound * (1.0 + 2.0 * delta) + tiny;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(a.item_queue, 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= total) break;
+        const int r = a.irep ? a.irep[item] : item_rep(a, item);
+        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kTileQ;
+        const int q_end = a.roff[r + 1];
+        const int p = q_begin + (int)threadIdx.x;
+        const bool valid = p < q_end;
+        const int q = a.qlist[valid ? p : q_end - 1];
+        f4 qv[F4];
+        valu_load_q<KS>(qv, a.Q, a.ldq, a.d, q);
+        const float* qp = a.Q + (int64_t)q * a.ldq;
+        const int r0 = a.list_off[r], r1 = a.list_off[r + 1];
+        int hits = 0;
+        for (int base = r0; base < r1; base += kRowsValu) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < kRowsValu * F4; e += 256) {
+                const int rr = e / F4, cc = e - rr * F4;
+                const int row = base + rr;
+                f4 v = {0.f, 0.f, 0.f, 0.f};
+                if (row < r1 && 4 * cc < a.d) v = *(const f4*)(a.X + (int64_t)row * a.ldx + 4 * cc);
+                xs[e] = v;
+            }
+            __syncthreads();
+            if (!valid) continue;
+            const int nrow = r1 - base < kRowsValu ? r1 - base : kRowsValu;
+            for (int t = 0; t < nrow; ++t) {
+                f4 s4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < F4; ++j) {
+                    const f4 df = qv[j] - xs[t * F4 + j];
+                    if (METRIC == 0) {
+                        s4 = df * df + s4;
+                    } else {
+                        s4[0] += __builtin_fabsf(df[0]);
+                        s4[1] += __builtin_fabsf(df[1]);
+                        s4[2] += __builtin_fabsf(df[2]);
+                        s4[3] += __builtin_fabsf(df[3]);
+                    }
+                }
+                const double sv = (double)((s4[0] + s4[1]) + (s4[2] + s4[3]));
+                if (sv > b_out && sv < __builtin_huge_val()) continue;
+                const int row = base + t;
+                // both passes take the same decision for every row, so the
+                // fill pass meets exactly the counts of the count pass
+                const bool sure = sv <= b_in;
+                double rho = 0.0;
+                if (!sure || a.range_fill) rho = rho_fp64(qp, a.X + (int64_t)row * a.ldx, a.d, METRIC);
+                if (!sure && !(rho <= a.range_radius)) continue;
+                if (a.range_fill) {
+                    // the cursor stays inside the caller's segment of query q;
+                    // a hit beyond it (offsets from another radius or index)
+                    // is counted in range_cnt[m] instead of written
+                    const int64_t pos = a.range_off[q] + atomicAdd(a.range_cnt + q, 1);
+                    if (pos < a.range_off[q + 1]) {
+                        a.range_idx[pos] = a.ids[row];
+                        a.range_dist[pos] = (float)rho;
+                    } else {
+                        atomicAdd(a.range_cnt + a.m, 1);
+                    }
+                } else {
+                    ++hits;
+                }
+            }
+        }
+        if (!a.range_fill && valid && hits) atomicAdd(a.range_cnt + q, hits);
+    }
+}
+
 template <int METRIC, int C>
 static hipError_t launch_c(int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
     if (mode == kTileItems)
@@ -180,6 +275,10 @@ template <int METRIC>
 static hipError_t launch_m(int c, int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
     if (mode == kTileAll) {
         hipLaunchKernelGGL((tile_valu_all<METRIC, RBC_KS>), grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    if (mode == kTileRange) {
+        hipLaunchKernelGGL((tile_valu_range<METRIC, RBC_KS>), grid, dim3(256), 0, st, a);
         return hipGetLastError();
     }
     switch (c) {

@@ -24,6 +24,7 @@ constexpr int kExactKCap = 1024;
 constexpr int kTileBF = 0;     // partial shortlists per (split, query)
 constexpr int kTileItems = 1;  // persistent (representative, query chunk) items
 constexpr int kTileAll = 2;    // every value written to pval[q * ldo + row]
+constexpr int kTileRange = 3;  // range search items: count, or write, the rows within a radius
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -71,6 +72,17 @@ struct TileArgs {
     // whose (query block, split) layout is derived from the count (dev_split)
     const int32_t* m_dev;
     int32_t dev_blocks;
+    // Range mode (kTileRange, vector path): every row of an item's list within
+    // range_radius of a query is counted (range_fill 0: range_cnt[q] += hits)
+    // or written (range_fill 1: at range_off[q] + a cursor taken from
+    // range_cnt[q], id ids[row], float64 distance rounded to float)
+    int32_t range_fill;
+    double range_radius;
+    int32_t* range_cnt;
+    const int64_t* range_off;
+    int64_t* range_idx;
+    float* range_dist;
+    const int64_t* ids;
 };
 
 // Merge of the partial shortlists, direct re-score, float64 near-tie

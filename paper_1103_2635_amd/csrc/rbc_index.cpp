@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -796,6 +797,140 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                         st);
 }
 
+// ---------------------------------------------------------------- range search
+// Scratch of one range call: stage 1, pruning and the work list as for the
+// k-NN search, plus the per-query hit counters (and an overflow counter).
+struct RangeWork {
+    float* Qp = nullptr;
+    int32_t* counters = nullptr;
+    float* DR = nullptr;
+    int32_t* lrank = nullptr;
+    uint8_t* keep_rq = nullptr;
+    int32_t* npairs = nullptr;
+    int32_t* roff = nullptr;
+    int32_t* ioff = nullptr;
+    int32_t* qlist = nullptr;
+    int32_t* irep = nullptr;
+    int32_t* cnt = nullptr;  // m + 1
+};
+
+struct RangePlan {
+    int ks;
+    bool repack;
+    int64_t ldp;
+};
+
+int range_plan(const rbc_index* ix, int64_t m, int64_t ldq, RangePlan* rp) {
+    if (!ix) return set_err(RBC_EINVAL, "index is NULL");
+    if (m < 0) return set_err(RBC_EINVAL, "m < 0");
+    if (ldq < ix->d) return set_err(RBC_EINVAL, "ldq smaller than d");
+    if (ix->mode != RBC_EXACT) return set_err(RBC_EUNSUPPORTED, "range search needs an exact index");
+    rp->ks = (ix->d + 15) / 16;
+    if (rp->ks > kMaxKS) return set_err(RBC_EUNSUPPORTED, "range search supports d <= 128");
+    if ((int64_t)m * ix->n_r >= ((int64_t)1 << 31))
+        return set_err(RBC_EUNSUPPORTED, "m * n_r >= 2^31: split the query batch");
+    rp->ldp = ((int64_t)ix->d + 3) / 4 * 4;
+    rp->repack = (ix->d % 4) != 0 || (ldq % 4) != 0;
+    return RBC_OK;
+}
+
+void carve_range(const rbc_index* ix, const RangePlan& rp, int64_t m, Carver& cv, RangeWork* w) {
+    const int64_t nr = ix->n_r;
+    if (rp.repack) w->Qp = cv.take<float>(m * rp.ldp);
+    w->counters = cv.take<int32_t>(kCounters);
+    w->DR = cv.take<float>(m * stage1_ld(nr));
+    w->lrank = cv.take<int32_t>(m * nr);
+    w->keep_rq = cv.take<uint8_t>(m * nr);
+    w->npairs = cv.take<int32_t>(m);
+    w->roff = cv.take<int32_t>(nr + 1);
+    w->ioff = cv.take<int32_t>(nr + 1);
+    w->qlist = cv.take<int32_t>(m * nr);
+    w->irep = cv.take<int32_t>(m * nr / kTileQ + nr + 1);
+    w->cnt = cv.take<int32_t>(m + 1);
+}
+
+int range_args(const rbc_index* ix, const RangePlan& rp, const float* Q, int64_t m, int64_t ldq,
+               double radius, void* workspace, size_t ws_bytes, RangeWork* w) {
+    if (!std::isfinite(radius) || radius < 0.0)
+        return set_err(RBC_EINVAL, "radius must be finite and >= 0");
+    if (m > 0 && !Q) return set_err(RBC_EINVAL, "Q is NULL");
+    if ((uintptr_t)Q & 15) return set_err(RBC_EINVAL, "Q must be 16-byte aligned");
+    Carver cv((char*)workspace);
+    carve_range(ix, rp, m, cv, w);
+    if (!workspace || ws_bytes < cv.size())
+        return set_err(RBC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu needed",
+                       ws_bytes, cv.size());
+    return RBC_OK;
+}
+
+// Stage 1, pruning for the radius, work list, then one pass of the range tile
+// (fill = 0: count into w.cnt; fill = 1: write at offsets).
+int range_pass(const rbc_index* ix, const RangePlan& rp, const float* Q, int64_t m, int64_t ldq,
+               double radius, int fill, const int64_t* offsets, int64_t* out_idx,
+               float* out_dist, RangeWork& w, hipStream_t st) {
+    const int32_t nr = (int32_t)ix->n_r;
+    const double delta = 2.0 * (ix->d + 2) * 5.9604644775390625e-8;
+    const int64_t ldd = stage1_ld(nr);
+    int rc;
+    const float* Qk = Q;
+    int64_t ldqk = ldq;
+    if (rp.repack) {
+        if ((rc = check(launch_repack(Q, m, ldq, ix->d, w.Qp, rp.ldp, st), "repack Q"))) return rc;
+        Qk = w.Qp;
+        ldqk = rp.ldp;
+    }
+    if ((rc = check(launch_fill_i32(w.counters, kCounters, 0, st), "clear counters"))) return rc;
+    if ((rc = check(launch_fill_i32(w.cnt, m + 1, 0, st), "clear hit counts"))) return rc;
+    {
+        KernelTimer kt("stage1", st);
+        if ((rc = check(launch_dist_all(ix->metric, Q, ldq, (int32_t)m, ix->R, ix->ld, nr, ix->d,
+                                        w.DR, ldd, st), "stage 1")))
+            return rc;
+    }
+    {
+        KernelTimer kt("prune", st);
+        if ((rc = check(launch_prune_range(w.DR, ldd, (int32_t)m, nr, delta, ix->psi, radius,
+                                           w.lrank, w.npairs, nullptr, st), "range prune")))
+            return rc;
+        if ((rc = check(launch_keep_transpose(w.lrank, (int32_t)m, nr, w.keep_rq, st), "keep")))
+            return rc;
+    }
+    {
+        KernelTimer kt("worklist", st);
+        if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, kTileQ, w.roff, w.ioff,
+                                        w.qlist, st), "work list")))
+            return rc;
+        if ((rc = check(launch_item_reps(w.ioff, nr, w.irep, st), "item reps"))) return rc;
+    }
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = Qk;
+    a.ldq = ldqk;
+    a.m = (int32_t)m;
+    a.X = ix->Xp;
+    a.ldx = ix->ld;
+    a.n = (int32_t)ix->rows;
+    a.d = ix->d;
+    a.item_total = w.ioff + nr;
+    a.item_queue = w.counters + 2;
+    a.irep = w.irep;
+    a.ioff = w.ioff;
+    a.roff = w.roff;
+    a.qlist = w.qlist;
+    a.list_off = ix->list_off;
+    a.n_r = nr;
+    a.range_fill = fill;
+    a.range_radius = radius;
+    a.range_cnt = w.cnt;
+    a.range_off = offsets;
+    a.range_idx = out_idx;
+    a.range_dist = out_dist;
+    a.ids = ix->ids;
+    KernelTimer kt("range_tile", st);
+    return check(launch_tile_valu(ix->metric, rp.ks, 0, kTileRange, dim3(kItemBlocks), a, st),
+                 "range tile");
+}
+
 }  // namespace
 
 extern "C" {
@@ -911,6 +1046,75 @@ int rbc_search(const rbc_index* ix, const float* Q, int64_t m, int64_t ldq, int3
             return run_bf(p, Q, m, ldq, ix->Xp, ix->rows, ix->ld, nullptr, nullptr, ix->ids,
                           out_idx, out_dist, w.bf, stats, st);
         return search_exact(ix, p, Q, m, ldq, k, out_idx, out_dist, w, stats, st);
+    } catch (...) {
+        return set_err(RBC_EHIP, "unexpected exception");
+    }
+}
+
+int rbc_range_workspace_size(const rbc_index* ix, int64_t m, int64_t ldq, size_t* bytes) {
+    try {
+        if (!bytes) return set_err(RBC_EINVAL, "bytes is NULL");
+        RangePlan rp;
+        int rc = range_plan(ix, m, ldq, &rp);
+        if (rc) return rc;
+        Carver cv(nullptr);
+        RangeWork w;
+        carve_range(ix, rp, m, cv, &w);
+        *bytes = cv.size();
+        return RBC_OK;
+    } catch (...) {
+        return set_err(RBC_EHIP, "unexpected exception");
+    }
+}
+
+int rbc_range_count(const rbc_index* ix, const float* Q, int64_t m, int64_t ldq, double radius,
+                    int64_t* offsets, void* workspace, size_t ws_bytes, void* hip_stream) {
+    try {
+        RangePlan rp;
+        int rc = range_plan(ix, m, ldq, &rp);
+        if (rc) return rc;
+        if (!offsets) return set_err(RBC_EINVAL, "offsets is NULL");
+        RangeWork w;
+        if ((rc = range_args(ix, rp, Q, m, ldq, radius, workspace, ws_bytes, &w))) return rc;
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (m > 0 && (rc = range_pass(ix, rp, Q, m, ldq, radius, 0, nullptr, nullptr, nullptr, w,
+                                      st)))
+            return rc;
+        return check(launch_offsets64(w.cnt, m, offsets, st), "range offsets");
+    } catch (...) {
+        return set_err(RBC_EHIP, "unexpected exception");
+    }
+}
+
+int rbc_range_search(const rbc_index* ix, const float* Q, int64_t m, int64_t ldq, double radius,
+                     const int64_t* offsets, int64_t* out_idx, float* out_dist, void* workspace,
+                     size_t ws_bytes, void* hip_stream) {
+    try {
+        RangePlan rp;
+        int rc = range_plan(ix, m, ldq, &rp);
+        if (rc) return rc;
+        if (m == 0) return RBC_OK;
+        if (!offsets || !out_idx || !out_dist) return set_err(RBC_EINVAL, "NULL pointer");
+        RangeWork w;
+        if ((rc = range_args(ix, rp, Q, m, ldq, radius, workspace, ws_bytes, &w))) return rc;
+        hipStream_t st = (hipStream_t)hip_stream;
+        if ((rc = range_pass(ix, rp, Q, m, ldq, radius, 1, offsets, out_idx, out_dist, w, st)))
+            return rc;
+        {
+            KernelTimer kt("range_sort", st);
+            if ((rc = check(launch_seg_sort_pairs(offsets, m, out_idx, out_dist, w.cnt, w.cnt + m,
+                                                  st), "range sort")))
+                return rc;
+        }
+        int32_t over = 0;
+        if ((rc = check(hipMemcpyAsync(&over, w.cnt + m, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                       st), "read overflow")))
+            return rc;
+        if ((rc = check(hipStreamSynchronize(st), "range search"))) return rc;
+        if (over)
+            return set_err(RBC_EINVAL, "%d points or segments do not match the offsets (offsets "
+                           "from another index, query set or radius)", over);
+        return RBC_OK;
     } catch (...) {
         return set_err(RBC_EHIP, "unexpected exception");
     }

@@ -76,6 +76,14 @@ hipError_t launch_psi_own(const float* Xp, int64_t ld, int32_t d, int32_t metric
 hipError_t launch_gather_norms(const float* qn, const int32_t* perm, int64_t n, float* xn,
                                uint32_t* maxbits, const uint32_t* flags_in, uint32_t* flags_out,
                                hipStream_t st);
+// Range search: pruning (keep r when rho(q,r) - psi_r <= radius), int64
+// offsets from int32 counts, per-query sort of (dist, idx) pairs.
+hipError_t launch_prune_range(const float* DR, int64_t ldd, int32_t m, int32_t nr, double delta,
+                              const double* psi, double radius, int32_t* lrank, int32_t* nkept,
+                              int64_t* stats, hipStream_t st);
+hipError_t launch_offsets64(const int32_t* cnt, int64_t m, int64_t* off, hipStream_t st);
+hipError_t launch_seg_sort_pairs(const int64_t* off, int64_t nseg, int64_t* idx, float* dist,
+                                 const int32_t* cnt, int32_t* bad, hipStream_t st);
 // Stable sort of each segment of vals by a float key (see k_rbc.hip).
 hipError_t launch_seg_sort(const int32_t* off, int32_t nseg, int32_t* vals, const float* keys,
                            int64_t ldk, int32_t* sorted, hipStream_t st);

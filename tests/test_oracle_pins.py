@@ -90,6 +90,33 @@ def test_approx_search_properties(orc):
             np.testing.assert_allclose(dist[i], sub_d[0], rtol=1e-12)
 
 
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+def test_range_bf_matches_python(orc, metric):
+    """Range search against a pure-Python filter with math.fsum distances, on
+    small random inputs, including a radius that lands exactly on a distance
+    of integer data (the boundary belongs to the range)."""
+    import math
+
+    rng = np.random.default_rng(5)
+    X = rng.integers(0, 4, (40, 3)).astype(np.float32)
+    Q = rng.integers(0, 4, (6, 3)).astype(np.float32)
+    for radius in (0.0, 1.0, 2.0, 2.5):
+        off, idx, dist = orc.range_bf(Q, X, radius, metric)
+        for i, q in enumerate(Q):
+            want = []
+            for j, x in enumerate(X):
+                if metric == "l2":
+                    r = math.sqrt(math.fsum((float(a) - float(b)) ** 2 for a, b in zip(q, x)))
+                else:
+                    r = math.fsum(abs(float(a) - float(b)) for a, b in zip(q, x))
+                if r <= radius:
+                    want.append((r, j))
+            want.sort()
+            got = list(zip(dist[off[i]:off[i + 1]].tolist(), idx[off[i]:off[i + 1]].tolist()))
+            assert [j for _, j in got] == [j for _, j in want], (radius, i)
+            np.testing.assert_allclose([r for r, _ in got], [r for r, _ in want], rtol=1e-15)
+
+
 def test_worked_psi_zero_boundary(orc):
     """Strict pruning keeps the nearest representative that owns only itself;
     the literal non-strict rule empties the candidate set (planted mistake)."""
