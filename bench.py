@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="also sweep the approximate variant's eps and the number of "
                          "representatives n_r on the headline workload")
+    ap.add_argument("--range", action="store_true",
+                    help="also time the range search on the headline index at radii that hold "
+                         "about 1, 20 and 200 points per query")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -239,6 +242,7 @@ def main():
     serving = run_serving(rbc, torch, dev) if args.serving else None
     configs = run_configs(rbc, torch, dev) if args.configs else None
     sweep = run_sweeps(rbc, torch, dev, Xd, Qd, w, reps) if args.sweep else None
+    rng_line = run_range(rbc, torch, dev, Xd, Qd, w, reps) if args.range else None
 
     line = {
         "metric": "exact k-NN queries/s (n=1M, d=64), RBC build+search vs BF, recall 1.0",
@@ -280,6 +284,8 @@ def main():
         line["configs"] = configs
     if sweep:
         line["sweeps"] = sweep
+    if rng_line:
+        line["range"] = rng_line
     print(json.dumps(line))
 
 
@@ -342,6 +348,44 @@ def run_sweeps(rbc, torch, dev, Xd, Qd, w, reps):
     out["n_r"] = nr_rows
     out["workload"] = "sub8: n=1,000,000 d=64, m=10,000, l2, k=1"
     return out
+
+
+def run_range(rbc, torch, dev, Xd, Qd, w, reps):
+    """Range search on the headline index (L2): for radii equal to the median
+    1st, 20th and 200th nearest-neighbour distance of 256 queries, the time
+    of the two calls (count, then fill + sort; the caller reads the total in
+    between), points per query, and the library's kernel times."""
+    import numpy as np
+
+    sync = torch.cuda.synchronize
+    m = Qd.shape[0]
+    _, bd = rbc.bf_search(Qd[:256].contiguous(), Xd, 200, "l2")
+    sync()
+    bd = bd.cpu().numpy()
+    ix = rbc.rbc_build(Xd, w.n_r, rep_idx=reps)
+    ws = torch.empty(rbc.rbc_range_workspace_size(ix, m, Qd.stride(0)), dtype=torch.uint8,
+                     device=dev)
+    rows = []
+    for kth in (1, 20, 200):
+        radius = float(np.median(bd[:, kth - 1]))
+        holder = {}
+
+        def call():
+            holder["r"] = rbc.rbc_range_search(ix, Qd, radius, workspace=ws)
+
+        ms = _timed(call, 5, 2, sync)
+        total = int(holder["r"][0][-1].item())
+        rbc.timer_enable(True)
+        call()
+        sync()
+        kern = {kn: round(rbc.timer_read(kn)[0], 4)
+                for kn in ("stage1", "prune", "worklist", "range_tile", "range_sort")}
+        rbc.timer_enable(False)
+        rows.append({"radius": round(radius, 5), "points_per_query": round(total / m, 2),
+                     "ms": round(ms, 3), "qps": round(m / ms * 1e3, 1), "kernel_ms": kern})
+    ix.free()
+    return {"workload": "sub8: n=1,000,000 d=64, m=10,000, l2, n_r=1,000 (index resident)",
+            "radii": rows}
 
 
 MFMA_PEAK_TF = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}

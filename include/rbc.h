@@ -86,6 +86,10 @@ typedef enum {
 #define RBC_STAT_CASCADE    5  /* low precision: queries whose certificate failed and that the
                                   float32 tile re-ranked over all rows */
 
+/* rbc_search_opts.flags: search an exact index in one pass (every kept list
+ * scanned in full, pruning by gamma_k) instead of the default two passes. */
+#define RBC_FLAG_ONE_PASS 1
+
 /* Per-call search options.  Pass NULL for the defaults. */
 typedef struct rbc_search_opts {
     int32_t precision;  /* rbc_precision; default RBC_FP32 */
@@ -93,7 +97,7 @@ typedef struct rbc_search_opts {
                            k + 3; at least 8 for RBC_BF16, 32 for RBC_FP8_E4M3);
                            rounded up to one of 4, 8, 16, 32, 64, and >= k + 3 */
     int32_t splits;     /* database splits per query block (0 = automatic) */
-    int32_t flags;      /* reserved, must be 0 */
+    int32_t flags;      /* rbc_search: 0 or RBC_FLAG_ONE_PASS; bf_search: 0 */
     int64_t* dev_stats; /* optional DEVICE array of RBC_STATS_LEN int64 counters */
     float* dev_approx_dist; /* optional DEVICE m x k floats: the distance each result had in
                                the ranking tile, before re-scoring (not written for queries
@@ -178,6 +182,14 @@ int rbc_build(const float* X, int64_t n, int64_t ldx, int32_t d,
  *   of at least rbc_search_workspace_size() bytes.  Concurrent calls on
  *   different streams with different workspaces are safe (the index is
  *   read-only after rbc_build).
+ *   Exact float32 searches (prune_eps 0, flags 0) take two passes: pass 1
+ *   searches each query's nearest list in full, which bounds the k-th
+ *   neighbour distance by tau_q <= gamma_k; pass 2 applies both rules with
+ *   tau_q in place of gamma_k and, inside each kept list (rows ordered by
+ *   their distance to the representative), scans only the rows x with
+ *   abs(rho(x, r) - rho(q, r)) <= tau_q (triangle inequality); the nearest
+ *   list is searched again over that range.  Low precision, prune_eps > 0 and
+ *   RBC_FLAG_ONE_PASS search in one pass.
  *   opts->precision RBC_BF16 / RBC_FP8_E4M3 ranks the kept lists with the
  *   quantised rows built into an exact index (rbc_build_params.precisions);
  *   the answers stay exact (float32 re-score, certificate that includes the

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "librbc.so")
 L2, L1 = 0, 1
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 EXACT, ONESHOT = 0, 1
+FLAG_ONE_PASS = 1
 STATS_LEN = 8
 STAT_FALLBACK, STAT_NEARTIE, STAT_PAIRS, STAT_LISTS, STAT_CAND, STAT_CASCADE = 0, 1, 2, 3, 4, 5
 
@@ -105,12 +106,13 @@ def _mat(t, name):
     return t
 
 
-def _opts(precision="fp32", shortlist=0, splits=0, stats=None, approx_dist=None, prune_eps=0.0):
+def _opts(precision="fp32", shortlist=0, splits=0, stats=None, approx_dist=None, prune_eps=0.0,
+          one_pass=False):
     o = SearchOpts()
     o.precision = _PRECS[precision]
     o.shortlist = int(shortlist)
     o.splits = int(splits)
-    o.flags = 0
+    o.flags = FLAG_ONE_PASS if one_pass else 0
     o.prune_eps = float(prune_eps)
     if stats is not None:
         if stats.dtype != torch.int64 or not stats.is_cuda or stats.numel() < STATS_LEN:

@@ -575,7 +575,7 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
                                                     double delta, const double* psi,
                                                     const int32_t* list_off, int32_t* lrank,
                                                     int32_t* nkept, float* gcup, int64_t* stats,
-                                                    double shrink) {
+                                                    double shrink, const float* taud) {
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= m) return;
@@ -587,7 +587,10 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
     const float gc = c <= nr ? __uint_as_float(pc) : RBC_INF;
     const double g1_up = (double)g1 * (1.0 + delta);
     // shrink < 1: the approximate variant (bounds divided by 1 + eps)
-    const double gk_up = (double)gk * (1.0 + delta);
+    double gk_up = (double)gk * (1.0 + delta);
+    // taud: a bound on the k-th neighbour distance from the query's nearest
+    // list (two-pass search); any such bound may replace gamma_k in both rules
+    if (taud && (double)taud[q] < gk_up) gk_up = (double)taud[q];
     const double bound2 = (2.0 * gk_up + g1_up) * shrink;
     const double bound1 = gk_up * shrink;
     int running = 0;
@@ -625,17 +628,164 @@ __global__ __launch_bounds__(256) void prune_kernel(const float* DR, int64_t ldd
 hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
                         double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
                         int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st,
-                        double shrink) {
+                        double shrink, const float* taud) {
     const dim3 grid((m + 3) / 4);
     if (nr <= 1024)
         hipLaunchKernelGGL(prune_kernel<16>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
-                           psi, list_off, lrank, nkept, gcup, stats, shrink);
+                           psi, list_off, lrank, nkept, gcup, stats, shrink, taud);
     else if (nr <= 2048)
         hipLaunchKernelGGL(prune_kernel<32>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
-                           psi, list_off, lrank, nkept, gcup, stats, shrink);
+                           psi, list_off, lrank, nkept, gcup, stats, shrink, taud);
     else
         hipLaunchKernelGGL(prune_kernel<0>, grid, dim3(256), 0, st, DR, ldd, m, nr, k, c, delta,
-                           psi, list_off, lrank, nkept, gcup, stats, shrink);
+                           psi, list_off, lrank, nkept, gcup, stats, shrink, taud);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ two-pass exact search
+// home[q] = the nearest representative of q (lowest position among equal
+// stage-1 distances).  One wavefront per query.
+__global__ __launch_bounds__(256) void nearest_rep_kernel(const float* DR, int64_t ldd, int32_t m,
+                                                          int32_t nr, int32_t* home) {
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= m) return;
+    const float* row = DR + (int64_t)q * ldd;
+    float best = RBC_INF;
+    int bi = 0x7fffffff;
+    for (int r = lane; r < nr; r += 64) {
+        const float v = row[r];
+        if (v < best || (v == best && r < bi)) {
+            best = v;
+            bi = r;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob < best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    if (lane == 0) home[q] = bi < nr ? bi : 0;
+}
+
+hipError_t launch_nearest_rep(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t* home,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(nearest_rep_kernel, dim3((m + 3) / 4), dim3(256), 0, st, DR, ldd, m, nr,
+                       home);
+    return hipGetLastError();
+}
+
+// taud[q]: an upper bound on the distance of q's k-th nearest database point,
+// from the k-th value v of its nearest list's shortlist (k rows have a tile
+// value <= v): mode 0 (matrix tile, v ~ ||x||^2 - 2 q.x, absolute error <=
+// 4 (d + 2) u (||q|| + max ||x||)^2, u = 2^-24): sqrt(v + E + ||q||^2
+// (1 + (d + 2) u)); mode 1 (direct squared l2, relative error <= delta):
+// sqrt(v / (1 - delta)); mode 2 (direct l1): v / (1 - delta); each widened
+// by 1e-6 and rounded up to a float.  +inf when the list has fewer than k rows.
+__global__ void tau_home_kernel(const float* hval, int32_t c, int32_t k, int32_t m, int32_t mode,
+                                const float* qn, const uint32_t* xmax_bits, int32_t d,
+                                double delta, float* taud) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const double u = 5.9604644775390625e-8;
+    const float v = hval[(int64_t)q * c + (k - 1)];
+    double t = RBC_INF_D;
+    if (v < RBC_INF) {
+        if (mode == 0) {
+            const double n2 = (double)qn[q];
+            const double sq = __builtin_sqrt(n2) + (double)__uint_as_float(*xmax_bits);
+            const double e = 4.0 * (d + 2) * u * sq * sq;
+            t = __builtin_sqrt(fmax((double)v + e + n2 * (1.0 + (d + 2) * u), 0.0));
+        } else if (mode == 1) {
+            t = __builtin_sqrt(fmax((double)v / (1.0 - delta), 0.0));
+        } else {
+            t = fmax((double)v / (1.0 - delta), 0.0);
+        }
+        t *= 1.0 + 1e-6;
+    }
+    taud[q] = t < RBC_INF_D ? round_up_f(t) : RBC_INF;
+}
+
+hipError_t launch_tau_home(const float* hval, int32_t c, int32_t k, int32_t m, int32_t mode,
+                           const float* qn, const uint32_t* xmax_bits, int32_t d, double delta,
+                           float* taud, hipStream_t st) {
+    hipLaunchKernelGGL(tau_home_kernel, dim3((m + 255) / 256), dim3(256), 0, st, hval, c, k, m,
+                       mode, qn, xmax_bits, d, delta, taud);
+    return hipGetLastError();
+}
+
+// Row range of every stage-2 item (two-pass search): a point x of L_r can be
+// one of q's k nearest only when abs(rho(x, r) - rho(q, r)) <= taud[q]
+// (triangle inequality).  With own(x) and the stage-1 rho(q, r) both within a
+// relative rel of the exact distances, that holds only for own in
+// [max(0, rho~/(1 + rel) - t) (1 - rel), (rho~/(1 - rel) + t) (1 + rel)]; a
+// list sorted by own (lsorted[r]) keeps those rows in one run, and the item
+// scans the run covering all of its queries: irows[2 i], irows[2 i + 1].
+// Unsorted lists are scanned whole.  One wavefront per item, grid-stride.
+__global__ __launch_bounds__(256) void item_rows_kernel(
+    const int32_t* item_total, const int32_t* irep, const int32_t* ioff, const int32_t* roff,
+    const int32_t* qlist, int32_t isize, const int32_t* list_off, const int32_t* lsorted,
+    const float* own, const float* DR, int64_t ldd, const float* taud, double rel,
+    int32_t* irows) {
+    const int lane = threadIdx.x & 63;
+    const int total = *item_total;
+    const int nwave = gridDim.x * 4;
+    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < total; item += nwave) {
+        const int r = irep[item];
+        const int b = list_off[r], e = list_off[r + 1];
+        int lo = b, hi = e;
+        if (lsorted[r]) {
+            const int q_begin = roff[r] + (item - ioff[r]) * isize;
+            const int q_end = min(q_begin + isize, roff[r + 1]);
+            double vlo = RBC_INF_D, vhi = 0.0;
+            for (int p = q_begin + lane; p < q_end; p += 64) {
+                const int q = qlist[p];
+                const double rq = (double)DR[(int64_t)q * ldd + r];
+                const double t = (double)taud[q];
+                double l = (rq / (1.0 + rel) - t) * (1.0 - rel);
+                double h = (rq / (1.0 - rel) + t) * (1.0 + rel);
+                if (!(l > 0.0)) l = 0.0;          // also NaN
+                if (!(h < RBC_INF_D)) h = RBC_INF_D;
+                vlo = fmin(vlo, l);
+                vhi = fmax(vhi, h);
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                vlo = fmin(vlo, __shfl_xor(vlo, off));
+                vhi = fmax(vhi, __shfl_xor(vhi, off));
+            }
+            // first row with own >= vlo, first row with own > vhi
+            int l = b, h = e;
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if ((double)own[mid] < vlo) l = mid + 1; else h = mid;
+            }
+            lo = l;
+            h = e;
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if ((double)own[mid] <= vhi) l = mid + 1; else h = mid;
+            }
+            hi = l;
+        }
+        if (lane == 0) {
+            irows[2 * (int64_t)item] = lo;
+            irows[2 * (int64_t)item + 1] = hi;
+        }
+    }
+}
+
+hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, const int32_t* ioff,
+                            const int32_t* roff, const int32_t* qlist, int32_t isize,
+                            const int32_t* list_off, const int32_t* lsorted, const float* own,
+                            const float* DR, int64_t ldd, const float* taud, double rel,
+                            int32_t* irows, hipStream_t st) {
+    hipLaunchKernelGGL(item_rows_kernel, dim3(1024), dim3(256), 0, st, item_total, irep, ioff,
+                       roff, qlist, isize, list_off, lsorted, own, DR, ldd, taud, rel, irows);
     return hipGetLastError();
 }
 

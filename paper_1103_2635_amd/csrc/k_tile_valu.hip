@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(a.item_queue, 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // scalar loop control
         if (item >= total) break;
         const int r = a.irep ? a.irep[item] : item_rep(a, item);
         const int q_begin = a.roff[r] + (item - a.ioff[r]) * kTileQ;
@@ -108,8 +108,12 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         valu_load_q<KS>(qv, a.Q, a.ldq, a.d, q);
         TopC<C> top;
         if (a.tau) top.seed(a.tau[q]); else top.init();
-        valu_scan<METRIC, KS, C>(qv, a.X, a.ldx, a.d, a.list_off[r], a.list_off[r + 1], valid, top,
-                                 xs);
+        int r0 = a.list_off[r], r1 = a.list_off[r + 1];
+        if (a.irows) {  // the same entries for the whole workgroup
+            r0 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item]);
+            r1 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item + 1]);
+        }
+        if (r0 < r1) valu_scan<METRIC, KS, C>(qv, a.X, a.ldx, a.d, r0, r1, valid, top, xs);
         if (valid) {
             const int64_t pair =
                 a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r] : (int64_t)q;
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         if (a.stats && threadIdx.x == 0) {
             const int nq = q_end - q_begin < kTileQ ? q_end - q_begin : kTileQ;
             atomicAdd((unsigned long long*)&a.stats[2],
-                      (unsigned long long)nq * (a.list_off[r + 1] - a.list_off[r]));
+                      (unsigned long long)nq * (r1 > r0 ? r1 - r0 : 0));
         }
     }
 }

@@ -50,8 +50,9 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
         return set_err(RBC_EINVAL, "unknown precision %d", prec);
     if (prec != RBC_FP32 && (metric != RBC_L2 || d > 128))
         return set_err(RBC_EUNSUPPORTED, "low precision needs the L2 metric and d <= 128");
-    if (opts && (opts->flags != 0 || opts->reserved != 0))
-        return set_err(RBC_EINVAL, "opts->flags and opts->reserved must be 0");
+    if (opts && ((opts->flags & ~RBC_FLAG_ONE_PASS) != 0 || opts->reserved != 0))
+        return set_err(RBC_EINVAL, "opts->flags must be 0 or RBC_FLAG_ONE_PASS, opts->reserved 0");
+    p->one_pass = opts && (opts->flags & RBC_FLAG_ONE_PASS);
     if (opts && !(opts->prune_eps >= 0.0f && opts->prune_eps < 1e30f))
         return set_err(RBC_EINVAL, "opts->prune_eps must be finite and >= 0");
     p->prune_eps = opts ? (double)opts->prune_eps : 0.0;
@@ -437,7 +438,8 @@ int bf_search_workspace_size(int64_t m, int64_t n, int32_t d, int64_t ldq, int64
         BfPlan p;
         rc = make_bf_plan(m > 0 ? m : 1, n, d, ldq, ldx, metric, k, opts, &p);
         if (rc) return rc;
-        if (p.prune_eps != 0.0) return set_err(RBC_EINVAL, "prune_eps applies to rbc_search only");
+        if (p.prune_eps != 0.0 || p.one_pass)
+            return set_err(RBC_EINVAL, "prune_eps and flags apply to rbc_search only");
         Carver cv(nullptr);
         BfWork w;
         carve_bf(p, m, n, cv, &w);
@@ -462,7 +464,8 @@ int bf_search(const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
         BfPlan p;
         rc = make_bf_plan(m, n, d, ldq, ldx, metric, k, opts, &p);
         if (rc) return rc;
-        if (p.prune_eps != 0.0) return set_err(RBC_EINVAL, "prune_eps applies to rbc_search only");
+        if (p.prune_eps != 0.0 || p.one_pass)
+            return set_err(RBC_EINVAL, "prune_eps and flags apply to rbc_search only");
         Carver cv((char*)workspace);
         BfWork w;
         carve_bf(p, m, n, cv, &w);

@@ -53,6 +53,8 @@ struct TileArgs {
     const int32_t* item_total;
     int32_t* item_queue;
     const int32_t* irep;   // item -> representative (null: binary search over ioff)
+    const int32_t* irows;  // item mode, optional: item i scans rows irows[2 i] .. irows[2 i + 1]
+                           // (a run of its list) instead of the whole list
     const int32_t* ioff;
     const int32_t* roff;
     const int32_t* qlist;

@@ -138,6 +138,13 @@ __device__ __forceinline__ int item_rep(const TileArgs& a, int item) {
 // Makes this wavefront's LDS writes visible to its own later LDS reads (and
 // keeps the compiler from moving LDS accesses across the point).  LDS
 // operations of one wavefront are executed in issue order.
+// The smallest float not below x (x >= 0, finite).
+__device__ __forceinline__ float round_up_f(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = __uint_as_float(__float_as_uint(f) + 1u);
+    return f;
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

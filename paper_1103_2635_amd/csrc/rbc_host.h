@@ -69,6 +69,8 @@ struct BfPlan {
     int64_t ldc;       // row length of the compacted query copies (d rounded up to 4)
     int32_t casc_blocks;  // its workgroups
     double prune_eps;     // exact RBC search: pruning bounds divided by (1 + eps)
+    bool one_pass;        // RBC_FLAG_ONE_PASS given
+    bool two_pass;        // exact RBC search in two passes (set by the index's planner)
 };
 
 struct BfWork {

@@ -445,6 +445,17 @@ struct SearchWork {
     int32_t* ioff = nullptr;     // n_r + 1
     int32_t* qlist = nullptr;    // up to m * n_r
     int32_t* irep = nullptr;     // item -> representative
+    // two-pass search: pass 1 over each query's nearest list
+    int32_t* home = nullptr;     // m: nearest representative
+    int32_t* qa = nullptr;       // m: queries grouped by home
+    int32_t* roffa = nullptr;    // n_r + 1
+    int32_t* ioffa = nullptr;    // n_r + 1
+    int32_t* irepa = nullptr;    // pass-1 item -> representative
+    int32_t* csa = nullptr;      // counting-sort scratch
+    float* hval = nullptr;       // m x c: pass-1 shortlists
+    int32_t* hidx = nullptr;
+    float* taud = nullptr;       // m: bound on the k-th neighbour distance
+    int32_t* irows = nullptr;    // 2 per pass-2 item: its row run
 };
 
 int64_t stage1_ld(int64_t nr) { return (nr + 3) / 4 * 4; }
@@ -598,6 +609,18 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
     w->ioff = cv.take<int32_t>(nr + 1);
     w->qlist = cv.take<int32_t>(m * nr);
     w->irep = cv.take<int32_t>(m * nr / kWave + nr + 1);
+    if (p.two_pass) {
+        w->home = cv.take<int32_t>(m);
+        w->qa = cv.take<int32_t>(m);
+        w->roffa = cv.take<int32_t>(nr + 1);
+        w->ioffa = cv.take<int32_t>(nr + 1);
+        w->irepa = cv.take<int32_t>(m / kWave + nr + 1);
+        w->csa = cv.take<int32_t>(csort_scratch(m, (int32_t)nr));
+        w->hval = cv.take<float>(m * p.c);
+        w->hidx = cv.take<int32_t>(m * p.c);
+        w->taud = cv.take<float>(m);
+        w->irows = cv.take<int32_t>(2 * (m * nr / kWave + nr + 1));
+    }
 }
 
 int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
@@ -610,8 +633,8 @@ int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
     }
     if (ix->mode == RBC_ONESHOT && k > ix->s)
         return set_err(RBC_EINVAL, "one-shot search needs k <= s (%lld)", (long long)ix->s);
-    if (ix->mode == RBC_ONESHOT && opts && opts->prune_eps != 0.0f)
-        return set_err(RBC_EINVAL, "prune_eps applies to exact indexes");
+    if (ix->mode == RBC_ONESHOT && opts && (opts->prune_eps != 0.0f || opts->flags != 0))
+        return set_err(RBC_EINVAL, "prune_eps and flags apply to exact indexes");
     if (ix->mode == RBC_EXACT && (int64_t)m * ix->n_r >= ((int64_t)1 << 31))
         return set_err(RBC_EUNSUPPORTED, "m * n_r >= 2^31: split the query batch");
     int rc = make_bf_plan(m > 0 ? m : 1, ix->rows, ix->d, ldq, ix->ld, ix->metric, k, opts, p);
@@ -620,6 +643,8 @@ int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
         p->casc = true;
         p->ldc = ((int64_t)ix->d + 3) / 4 * 4;
     }
+    p->two_pass = ix->mode == RBC_EXACT && (p->path == kPathMfma || p->path == kPathValu) &&
+                  p->prune_eps == 0.0 && !p->one_pass;
     return RBC_OK;
 }
 
@@ -687,8 +712,58 @@ int search_exact_lowp(const rbc_index* ix, const BfPlan& p, const float* Q, int6
                         st);
 }
 
-// Exact search, Sec. 5.2: stage 1 (all representative distances), pruning,
-// work list, grouped persistent stage-2 tile, finalize, fallback.
+// Pass 1 of the two-pass exact search: every query searches the list of its
+// nearest representative in full (queries grouped by that representative, one
+// persistent launch, one shortlist per query), and the k-th value of that
+// shortlist becomes taud[q], an upper bound on the distance of q's k-th
+// nearest point (k points of X lie within it).
+int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t ldqk, int64_t m,
+                 int32_t k, SearchWork& w, double delta, int64_t ldd, hipStream_t st) {
+    const int32_t nr = (int32_t)ix->n_r;
+    const int32_t isize = p.path == kPathValu ? kTileQ : kWave;
+    KernelTimer kt("pass1", st);
+    int rc;
+    if ((rc = check(launch_nearest_rep(w.DR, ldd, (int32_t)m, nr, w.home, st), "nearest rep")))
+        return rc;
+    if ((rc = check(launch_csort(w.home, m, nr, w.csa, w.qa, w.roffa, st), "group by home")))
+        return rc;
+    if ((rc = check(launch_items_from_offsets(w.roffa, nr, isize, w.ioffa, st), "pass-1 items")))
+        return rc;
+    if ((rc = check(launch_item_reps(w.ioffa, nr, w.irepa, st), "pass-1 item reps"))) return rc;
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Q = Qk;
+    a.ldq = ldqk;
+    a.m = (int32_t)m;
+    a.X = ix->Xp;
+    a.ldx = ix->ld;
+    a.n = (int32_t)ix->rows;
+    a.d = ix->d;
+    a.xn = ix->xn;
+    a.item_total = w.ioffa + nr;
+    a.item_queue = w.bf.counters + 3;
+    a.irep = w.irepa;
+    a.ioff = w.ioffa;
+    a.roff = w.roffa;
+    a.qlist = w.qa;
+    a.list_off = ix->list_off;
+    a.n_r = nr;
+    a.pval = w.hval;
+    a.pidx = w.hidx;
+    const dim3 grid(kItemBlocks);
+    rc = p.path == kPathMfma
+             ? check(launch_tile_mfma(p.ks, p.c, kTileItems, grid, a, st), "pass 1 (mfma)")
+             : check(launch_tile_valu(p.metric, p.ks, p.c, kTileItems, grid, a, st),
+                     "pass 1 (valu)");
+    if (rc) return rc;
+    const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
+    return check(launch_tau_home(w.hval, p.c, k, (int32_t)m, mode, w.bf.qn, ix->norms_max, ix->d,
+                                 delta, w.taud, st), "k-th neighbour bound");
+}
+
+// Exact search, Sec. 5.2: stage 1 (all representative distances), [pass 1
+// over the nearest lists], pruning, work list, grouped persistent stage-2
+// tile, finalize, fallback.
 int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m, int64_t ldq,
                  int32_t k, int64_t* out_idx, float* out_dist, SearchWork& w, int64_t* stats,
                  hipStream_t st) {
@@ -710,11 +785,16 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                                         w.DR, ldd, st), "stage 1")))
             return rc;
     }
+    if (p.path == kPathMfma &&
+        (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st,
+                                     (uint32_t*)w.bf.counters + 5), "norms Q")))
+        return rc;
+    if (p.two_pass && (rc = search_pass1(ix, p, Qk, ldqk, m, k, w, delta, ldd, st))) return rc;
     {
         KernelTimer kt("prune", st);
         if ((rc = check(launch_prune(w.DR, ldd, (int32_t)m, nr, k, p.c, delta, ix->psi,
                                      ix->list_off, w.lrank, w.npairs, w.gcup, stats, st,
-                                     1.0 / (1.0 + p.prune_eps)),
+                                     1.0 / (1.0 + p.prune_eps), p.two_pass ? w.taud : nullptr),
                         "prune")))
             return rc;
         if ((rc = check(launch_keep_transpose(w.lrank, (int32_t)m, nr, w.keep_rq, st), "keep")))
@@ -730,7 +810,18 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
         if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, isize, w.roff, w.ioff, w.qlist,
                                         st), "work list")))
             return rc;
+        // two-pass: the queries of each list in order of rho(q, r), so the
+        // row runs of one item's queries overlap
+        if (p.two_pass &&
+            (rc = check(launch_seg_sort(w.roff, nr, w.qlist, w.DR, ldd, nullptr, st),
+                        "order queries")))
+            return rc;
         if ((rc = check(launch_item_reps(w.ioff, nr, w.irep, st), "item reps"))) return rc;
+        if (p.two_pass &&
+            (rc = check(launch_item_rows(w.ioff + nr, w.irep, w.ioff, w.roff, w.qlist, isize,
+                                         ix->list_off, ix->lsorted, ix->own, w.DR, ldd, w.taud,
+                                         2.0 * delta, w.irows, st), "item rows")))
+            return rc;
         if (p.path == kPathLowp) {
             const rbc_index::Quant& qc = ix->quant[p.prec];
             uint32_t* ctr = (uint32_t*)w.bf.counters;
@@ -743,10 +834,6 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                             "thresholds")))
                 return rc;
         }
-        if (p.path == kPathMfma &&
-            (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st,
-                                         (uint32_t*)w.bf.counters + 5), "norms Q")))
-            return rc;
         const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
         if (p.path != kPathLowp &&
             (rc = check(launch_tau(w.gcup, w.bf.qn, ix->norms_max,
@@ -779,6 +866,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     a.pval = w.bf.pval;
     a.pidx = w.bf.pidx;
     a.stats = stats;
+    a.irows = p.two_pass ? w.irows : nullptr;
     {
         KernelTimer kt("tile_items", st);
         const dim3 grid(kItemBlocks);

@@ -41,7 +41,19 @@ hipError_t launch_dist_all(int metric, const float* Q, int64_t ldq, int32_t m, c
 hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t k, int32_t c,
                         double delta, const double* psi, const int32_t* list_off, int32_t* lrank,
                         int32_t* nkept, float* gcup, int64_t* stats, hipStream_t st,
-                        double shrink = 1.0);
+                        double shrink = 1.0, const float* taud = nullptr);
+// Two-pass exact search: nearest representative per query, the k-th
+// neighbour bound from the nearest list's shortlist, stage-2 item row ranges.
+hipError_t launch_nearest_rep(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t* home,
+                              hipStream_t st);
+hipError_t launch_tau_home(const float* hval, int32_t c, int32_t k, int32_t m, int32_t mode,
+                           const float* qn, const uint32_t* xmax_bits, int32_t d, double delta,
+                           float* taud, hipStream_t st);
+hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, const int32_t* ioff,
+                            const int32_t* roff, const int32_t* qlist, int32_t isize,
+                            const int32_t* list_off, const int32_t* lsorted, const float* own,
+                            const float* DR, int64_t ldd, const float* taud, double rel,
+                            int32_t* irows, hipStream_t st);
 hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
                                  hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.

@@ -261,10 +261,15 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         const int q = a.qlist[valid ? p : q_end - 1];
         TopC<C> top;
         if (a.tau) top.seed(a.tau[q]); else top.init();
+        int r0 = a.list_off[r], r1 = a.list_off[r + 1];
+        if (a.irows) {
+            r0 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item]);
+            r1 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item + 1]);
+        }
         // next ticket: issued after this item's metadata loads (memory
         // counters retire in issue order), consumed at the next iteration
         if (lane == 0) ticket = atomicAdd(a.item_queue, 1);
-        scan_rows<P, C>(qf, a, a.list_off[r], a.list_off[r + 1], valid, top, tbuf_wave, lane);
+        if (r0 < r1) scan_rows<P, C>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
         if (valid) {
             const int64_t pair =
                 a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r] : (int64_t)q;
@@ -273,7 +278,7 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         if (a.stats && lane == 0) {
             const int nq = q_end - q_begin < kWave ? q_end - q_begin : kWave;
             atomicAdd((unsigned long long*)&a.stats[2],
-                      (unsigned long long)nq * (a.list_off[r + 1] - a.list_off[r]));
+                      (unsigned long long)nq * (r1 > r0 ? r1 - r0 : 0));
         }
     }
 }

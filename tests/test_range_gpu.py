@@ -168,3 +168,24 @@ def test_range_errors(rbc):
     rc = rbc.lib().rbc_range_count(ix.handle, Q.data_ptr(), 64, 16, ctypes.c_double(1.0),
                                    off.data_ptr(), small.data_ptr(), small.numel(), None)
     assert rc == -5
+
+
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+def test_range_full_size_sampled(rbc, orc, metric):
+    """n=1,000,000 d=64 (8-dim subspace), n_r=1,000, all 10,000 queries at a
+    radius that holds about 20 points per query (the range line of the
+    bench); 32 sampled queries checked against the oracle's direct range
+    search one by one."""
+    X, Q = datagen.database("sub8"), datagen.queries("sub8")
+    reps = datagen.representatives("sub8")
+    _, d20 = orc.bf_knn(Q[:8], X, 20, metric)
+    radius = float(np.median(d20[:, -1]))
+    ix = rbc.rbc_build(_dev(X), 1000, metric=metric, rep_idx=reps)
+    off, idx, dist = _range(rbc, ix, Q, radius)
+    sample = np.sort(np.random.default_rng(31).choice(Q.shape[0], 32, replace=False))
+    r_off, r_idx, r_dist = orc.range_bf(Q[sample], X, radius, metric)
+    g_off = np.concatenate([[0], np.cumsum(off[sample + 1] - off[sample])])
+    g_idx = np.concatenate([idx[off[i]:off[i + 1]] for i in sample])
+    g_dist = np.concatenate([dist[off[i]:off[i + 1]] for i in sample])
+    _assert_range_parity((g_off, g_idx, g_dist), (r_off, r_idx, r_dist))
+    assert off[-1] > 10 * Q.shape[0]

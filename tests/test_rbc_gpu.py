@@ -95,20 +95,26 @@ CASES = [  # (workload, n, m, n_r)
 @pytest.mark.parametrize("metric", ["l2", "l1"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_exact_search_equals_bf(rbc, orc, metric, case):
-    """Exact search returns the brute-force answer; the kept lists are a
-    superset of the oracle's (the pruning bounds only widen)."""
+    """Exact search returns the brute-force answer, in one pass and in two.
+    One pass: the kept lists are a superset of the oracle's (the pruning
+    bounds only widen).  Two passes: the nearest list's bound on the k-th
+    neighbour distance keeps fewer lists and scores fewer pairs."""
     name, n, m, n_r = case
     X, Q = datagen.database(name, n), datagen.queries(name, m)
     reps = datagen.representatives(name, n, n_r)
     ix = rbc.rbc_build(_dev(X), n_r, metric=metric, rep_idx=reps)
     oix = orc.rbc_build_exact(X, reps, metric)
     for k in (1, 10):
-        idx, dist, st = _search(rbc, ix, Q, k)
         ref = orc.bf_knn(Q, X, k, metric)
+        idx, dist, st = _search(rbc, ix, Q, k, one_pass=True)
         assert_knn_parity(idx, dist, Q, X, k, metric, orc, ref=ref)
         _, _, ncand, nkept = orc.rbc_search_exact(Q, X, oix, k, metric)
         assert st[3] >= nkept.sum() and st[4] >= ncand.sum()
         assert st[4] <= 1.02 * ncand.sum() + 1000, (st[4], ncand.sum())
+        idx2, dist2, st2 = _search(rbc, ix, Q, k)
+        assert_knn_parity(idx2, dist2, Q, X, k, metric, orc, ref=ref)
+        assert st2[3] <= st[3] and st2[2] <= st[2], (st2, st)
+        print("%s %s k=%d pairs one-pass %d two-pass %d" % (name, metric, k, st[2], st2[2]))
 
 
 @pytest.mark.parametrize("metric", ["l2", "l1"])
