@@ -158,7 +158,8 @@ def main():
     sync()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     tile_ms, tile_n = rbc.timer_read("tile_items")
-    kernel_ms = {kn: rbc.timer_read(kn) for kn in ("stage1", "prune", "worklist", "finalize", "fallback")}
+    kernel_ms = {kn: rbc.timer_read(kn) for kn in ("stage1", "pass1", "prune", "worklist", "finalize",
+                                                   "fallback")}
     rbc.timer_enable(False)
     ix = holder["ix"]
 
@@ -193,13 +194,17 @@ def main():
 
     per_pair = 2 * d  # l2: one multiply-add per feature (2 flops); l1: subtract + abs-add
     tile_avg = tile_ms / max(tile_n, 1)
-    roofline = roof(per_pair * cand, tile_avg)
+    # stage 2 scores, for each work item, its queries against the run of rows
+    # of its list that the two-pass bound leaves (pairs); that is the work
+    roofline = roof(per_pair * pairs, tile_avg)
     roofline["traffic"] = (profiled_traffic("void rbc::tile_l2_mfma_items<4, 4>")
                            if (metric, k) == ("l2", 1) else None)
     roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)"
     roofline["kernel"] = "tile_l2_mfma_items (RBC stage 2)" if metric == "l2" else "tile_valu_items (RBC stage 2)"
     roofline["avg_ms"] = round(tile_avg, 4)
-    roofline["algorithmic_units"] = "2*d*sum_q candidates = %d flops per launch" % (per_pair * cand)
+    roofline["algorithmic_units"] = ("2*d per (query, row) pair scored: sum over items of "
+                                     "queries x rows of the item's run = %d pairs, %d flops per "
+                                     "launch" % (pairs, per_pair * pairs))
     bf_avg = bf_tile_ms / max(bf_tile_n, 1)
     bf_roof = roof(per_pair * m * n, bf_avg)
     bf_roof["avg_ms"] = round(bf_avg, 4)

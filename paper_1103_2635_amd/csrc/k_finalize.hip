@@ -111,13 +111,29 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     float part = 0.f;
     if (cvalid) {
         const float* cp = a.X + (int64_t)crow * a.ldx;
+        // rows as float4 runs when both are 16-byte aligned (sub-lane s takes
+        // runs s, s + LPC, ...), the tail as single features
+        const bool v4 = ((a.ldq | a.ldx) & 3) == 0 && (((uintptr_t)a.Q | (uintptr_t)a.X) & 15) == 0;
+        const int d4 = v4 ? a.d & ~3 : 0;
         if (a.metric == 0) {
-            for (int f = sub; f < a.d; f += LPC) {
+            for (int f = 4 * sub; f < d4; f += 4 * LPC) {
+                const f4 t = *(const f4*)(qp + f) - *(const f4*)(cp + f);
+                part = __builtin_fmaf(t[0], t[0], part);
+                part = __builtin_fmaf(t[1], t[1], part);
+                part = __builtin_fmaf(t[2], t[2], part);
+                part = __builtin_fmaf(t[3], t[3], part);
+            }
+            for (int f = d4 + sub; f < a.d; f += LPC) {
                 const float t = qp[f] - cp[f];
                 part = __builtin_fmaf(t, t, part);
             }
         } else {
-            for (int f = sub; f < a.d; f += LPC) part += __builtin_fabsf(qp[f] - cp[f]);
+            for (int f = 4 * sub; f < d4; f += 4 * LPC) {
+                const f4 t = *(const f4*)(qp + f) - *(const f4*)(cp + f);
+                part += __builtin_fabsf(t[0]) + __builtin_fabsf(t[1]) + __builtin_fabsf(t[2]) +
+                        __builtin_fabsf(t[3]);
+            }
+            for (int f = d4 + sub; f < a.d; f += LPC) part += __builtin_fabsf(qp[f] - cp[f]);
         }
     }
 #pragma unroll
@@ -233,13 +249,29 @@ __global__ __launch_bounds__(256) void finalize_group_kernel(FinArgs a) {
     float part = 0.f;
     if (cvalid) {
         const float* cp = a.X + (int64_t)crow * a.ldx;
+        // rows as float4 runs when both are 16-byte aligned (sub-lane s takes
+        // runs s, s + LPC, ...), the tail as single features
+        const bool v4 = ((a.ldq | a.ldx) & 3) == 0 && (((uintptr_t)a.Q | (uintptr_t)a.X) & 15) == 0;
+        const int d4 = v4 ? a.d & ~3 : 0;
         if (a.metric == 0) {
-            for (int f = sub; f < a.d; f += LPC) {
+            for (int f = 4 * sub; f < d4; f += 4 * LPC) {
+                const f4 t = *(const f4*)(qp + f) - *(const f4*)(cp + f);
+                part = __builtin_fmaf(t[0], t[0], part);
+                part = __builtin_fmaf(t[1], t[1], part);
+                part = __builtin_fmaf(t[2], t[2], part);
+                part = __builtin_fmaf(t[3], t[3], part);
+            }
+            for (int f = d4 + sub; f < a.d; f += LPC) {
                 const float t = qp[f] - cp[f];
                 part = __builtin_fmaf(t, t, part);
             }
         } else {
-            for (int f = sub; f < a.d; f += LPC) part += __builtin_fabsf(qp[f] - cp[f]);
+            for (int f = 4 * sub; f < d4; f += 4 * LPC) {
+                const f4 t = *(const f4*)(qp + f) - *(const f4*)(cp + f);
+                part += __builtin_fabsf(t[0]) + __builtin_fabsf(t[1]) + __builtin_fabsf(t[2]) +
+                        __builtin_fabsf(t[3]);
+            }
+            for (int f = d4 + sub; f < a.d; f += LPC) part += __builtin_fabsf(qp[f] - cp[f]);
         }
     }
 #pragma unroll

@@ -136,8 +136,9 @@ __global__ __launch_bounds__(64) void csort_scatter_kernel(const int32_t* keys, 
         const int32_t key = i < i1 ? keys[i] : -1;
         int rank = 0;
         bool last = true;
-        for (int j = 0; j < 64; ++j) {
-            const int32_t kj = __shfl(key, j);
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {  // constant source lanes: scalar lane reads
+            const int32_t kj = __builtin_amdgcn_readlane(key, j);
             if (kj == key) {
                 if (j < t) ++rank;
                 if (j > t) last = false;

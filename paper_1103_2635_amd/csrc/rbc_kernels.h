@@ -5,7 +5,7 @@
 
 namespace rbc {
 
-constexpr int kSortBlock = 4096;   // items per block of the stable counting sort
+constexpr int kSortBlock = 1024;   // items per block of the stable counting sort
 constexpr int kMaxReps = 16384;    // LDS histogram of the counting sort
 constexpr int kOsCap = 8192;       // one-shot build: candidates per representative (LDS sort)
 constexpr int kSegCap = 8192;      // longest segment of the LDS segmented sort
