@@ -246,15 +246,16 @@ hipError_t launch_oneshot_sort(const float* X, int64_t ldx, int32_t d, int32_t m
 
 // One-shot search work list: items per representative from the query counts
 // (offsets of the queries grouped by nearest representative).
-__global__ void os_items_kernel(const int32_t* roff, int32_t nr, int32_t isize, int32_t* nitems) {
+__global__ void os_items_kernel(const int32_t* roff, int32_t nr, int32_t isize, int32_t mult,
+                                int32_t* nitems) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nr) nitems[r] = (roff[r + 1] - roff[r] + isize - 1) / isize;
+    if (r < nr) nitems[r] = (roff[r + 1] - roff[r] + isize - 1) / isize * mult;
 }
 
 hipError_t launch_items_from_offsets(const int32_t* roff, int32_t nr, int32_t isize,
-                                     int32_t* ioff, hipStream_t st) {
+                                     int32_t* ioff, hipStream_t st, int32_t mult) {
     hipLaunchKernelGGL(os_items_kernel, dim3((nr + 255) / 256), dim3(256), 0, st, roff, nr, isize,
-                       ioff);
+                       mult, ioff);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_scan_total(ioff, nr, st);

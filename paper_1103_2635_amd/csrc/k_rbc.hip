@@ -681,19 +681,40 @@ hipError_t launch_nearest_rep(const float* DR, int64_t ldd, int32_t m, int32_t n
 }
 
 // taud[q]: an upper bound on the distance of q's k-th nearest database point,
-// from the k-th value v of its nearest list's shortlist (k rows have a tile
-// value <= v): mode 0 (matrix tile, v ~ ||x||^2 - 2 q.x, absolute error <=
+// from the k-th smallest value v over the nsplit sorted shortlists that cover
+// its nearest list (k rows have a tile value <= v): mode 0 (matrix tile, v ~ ||x||^2 - 2 q.x, absolute error <=
 // 4 (d + 2) u (||q|| + max ||x||)^2, u = 2^-24): sqrt(v + E + ||q||^2
 // (1 + (d + 2) u)); mode 1 (direct squared l2, relative error <= delta):
 // sqrt(v / (1 - delta)); mode 2 (direct l1): v / (1 - delta); each widened
 // by 1e-6 and rounded up to a float.  +inf when the list has fewer than k rows.
-__global__ void tau_home_kernel(const float* hval, int32_t c, int32_t k, int32_t m, int32_t mode,
-                                const float* qn, const uint32_t* xmax_bits, int32_t d,
-                                double delta, float* taud) {
+constexpr int kMaxHomeSplit = 8;
+
+__global__ void tau_home_kernel(const float* hval, int32_t c, int32_t nsplit, int32_t k,
+                                int32_t m, int32_t mode, const float* qn,
+                                const uint32_t* xmax_bits, int32_t d, double delta, float* taud) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= m) return;
     const double u = 5.9604644775390625e-8;
-    const float v = hval[(int64_t)q * c + (k - 1)];
+    // k-way merge of the sorted shortlists: the k-th value taken
+    const float* hv = hval + (int64_t)q * nsplit * c;
+    int pos[kMaxHomeSplit];
+    for (int s = 0; s < nsplit; ++s) pos[s] = 0;
+    float v = RBC_INF;
+    for (int t = 0; t < k; ++t) {
+        int bs = -1;
+        float bv = RBC_INF;
+        for (int s = 0; s < nsplit; ++s)
+            if (pos[s] < c && hv[s * c + pos[s]] < bv) {
+                bv = hv[s * c + pos[s]];
+                bs = s;
+            }
+        if (bs < 0) {
+            v = RBC_INF;
+            break;
+        }
+        ++pos[bs];
+        v = bv;
+    }
     double t = RBC_INF_D;
     if (v < RBC_INF) {
         if (mode == 0) {
@@ -711,11 +732,12 @@ __global__ void tau_home_kernel(const float* hval, int32_t c, int32_t k, int32_t
     taud[q] = t < RBC_INF_D ? round_up_f(t) : RBC_INF;
 }
 
-hipError_t launch_tau_home(const float* hval, int32_t c, int32_t k, int32_t m, int32_t mode,
-                           const float* qn, const uint32_t* xmax_bits, int32_t d, double delta,
-                           float* taud, hipStream_t st) {
-    hipLaunchKernelGGL(tau_home_kernel, dim3((m + 255) / 256), dim3(256), 0, st, hval, c, k, m,
-                       mode, qn, xmax_bits, d, delta, taud);
+hipError_t launch_tau_home(const float* hval, int32_t c, int32_t nsplit, int32_t k, int32_t m,
+                           int32_t mode, const float* qn, const uint32_t* xmax_bits, int32_t d,
+                           double delta, float* taud, hipStream_t st) {
+    if (nsplit < 1 || nsplit > kMaxHomeSplit) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tau_home_kernel, dim3((m + 255) / 256), dim3(256), 0, st, hval, c, nsplit,
+                       k, m, mode, qn, xmax_bits, d, delta, taud);
     return hipGetLastError();
 }
 

@@ -99,7 +99,12 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         const int item = __builtin_amdgcn_readfirstlane(s_item);  // scalar loop control
         if (item >= total) break;
         const int r = a.irep ? a.irep[item] : item_rep(a, item);
-        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kTileQ;
+        int chunk = item - a.ioff[r], split = 0;
+        if (a.isplit > 1) {
+            split = chunk % a.isplit;
+            chunk /= a.isplit;
+        }
+        const int q_begin = a.roff[r] + chunk * kTileQ;
         const int q_end = a.roff[r + 1];
         const int p = q_begin + (int)threadIdx.x;
         const bool valid = p < q_end;
@@ -112,11 +117,15 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         if (a.irows) {  // the same entries for the whole workgroup
             r0 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item]);
             r1 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item + 1]);
+        } else if (a.isplit > 1) {
+            const int64_t len = r1 - r0;
+            r1 = r0 + (int)(len * (split + 1) / a.isplit);
+            r0 = r0 + (int)(len * split / a.isplit);
         }
         if (r0 < r1) valu_scan<METRIC, KS, C>(qv, a.X, a.ldx, a.d, r0, r1, valid, top, xs);
         if (valid) {
-            const int64_t pair =
-                a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r] : (int64_t)q;
+            const int64_t pair = a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r]
+                                         : (int64_t)q * (a.isplit > 1 ? a.isplit : 1) + split;
             top.store(a.pval + pair * C, a.pidx + pair * C);
         }
         if (a.stats && threadIdx.x == 0) {

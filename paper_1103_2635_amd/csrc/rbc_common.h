@@ -55,6 +55,9 @@ struct TileArgs {
     const int32_t* irep;   // item -> representative (null: binary search over ioff)
     const int32_t* irows;  // item mode, optional: item i scans rows irows[2 i] .. irows[2 i + 1]
                            // (a run of its list) instead of the whole list
+    int32_t isplit;        // item mode without lrank, > 1: each query chunk of a list is
+                           // isplit items, item j scanning the j-th of isplit equal row
+                           // ranges and leaving its shortlist at pair q * isplit + j
     const int32_t* ioff;
     const int32_t* roff;
     const int32_t* qlist;

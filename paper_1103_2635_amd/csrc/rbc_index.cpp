@@ -218,9 +218,19 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     if ((rc = lay.commit(ix))) return rc;
     ix->rows = n;
 
-    // ownership: BF(X, R) with k = 1 (ties to the lower representative position)
+    // ownership: BF(X, R) with k = 1 (ties to the lower representative
+    // position).  For l2 the ranking runs on bf16 copies (the matrix cores'
+    // bf16 rate); the shortlist is re-scored in float32 and certified with the
+    // quantisation error included, uncertified points are ranked again in
+    // float32 and float64, so the owners are those of the exact search.
     BfPlan p;
-    if ((rc = make_bf_plan(n, n_r, d, ldx, ld, ix->metric, 1, nullptr, &p))) return rc;
+    rbc_search_opts own_opts;
+    std::memset(&own_opts, 0, sizeof(own_opts));
+    own_opts.precision = RBC_BF16;
+    own_opts.shortlist = 4;  // k = 1: the nearest owner is rarely within the bf16 error of a 5th
+    const bool own_bf16 = ix->metric == RBC_L2 && d <= 128;
+    if ((rc = make_bf_plan(n, n_r, d, ldx, ld, ix->metric, 1, own_bf16 ? &own_opts : nullptr, &p)))
+        return rc;
     int32_t *reps = nullptr, *owner = nullptr, *perm = nullptr, *cnt = nullptr;
     int64_t* own64 = nullptr;
     float* ownd = nullptr;
@@ -580,6 +590,14 @@ int search_oneshot(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t
     return run_fallback_lists(p, Q, m, ldq, ix, o.nearest, out_idx, out_dist, w.bf, st);
 }
 
+// Pass 1 of the two-pass search splits each nearest list into this many row
+// ranges (one work item each, about 128 rows or more), so that the few
+// queries of a list are served by several wavefronts.
+int home_splits(const rbc_index* ix) {
+    const int64_t per_list = ix->rows / std::max<int64_t>(ix->n_r, 1);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(8, per_list / 128));
+}
+
 void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, SearchWork* w) {
     if (p.path == kPathExact) {
         carve_bf(p, m, ix->rows, cv, &w->bf);
@@ -614,10 +632,10 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         w->qa = cv.take<int32_t>(m);
         w->roffa = cv.take<int32_t>(nr + 1);
         w->ioffa = cv.take<int32_t>(nr + 1);
-        w->irepa = cv.take<int32_t>(m / kWave + nr + 1);
+        w->irepa = cv.take<int32_t>((m / kWave + nr + 1) * home_splits(ix));
         w->csa = cv.take<int32_t>(csort_scratch(m, (int32_t)nr));
-        w->hval = cv.take<float>(m * p.c);
-        w->hidx = cv.take<int32_t>(m * p.c);
+        w->hval = cv.take<float>(m * home_splits(ix) * p.c);
+        w->hidx = cv.take<int32_t>(m * home_splits(ix) * p.c);
         w->taud = cv.take<float>(m);
         w->irows = cv.take<int32_t>(2 * (m * nr / kWave + nr + 1));
     }
@@ -727,7 +745,9 @@ int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t 
         return rc;
     if ((rc = check(launch_csort(w.home, m, nr, w.csa, w.qa, w.roffa, st), "group by home")))
         return rc;
-    if ((rc = check(launch_items_from_offsets(w.roffa, nr, isize, w.ioffa, st), "pass-1 items")))
+    const int ns = home_splits(ix);
+    if ((rc = check(launch_items_from_offsets(w.roffa, nr, isize, w.ioffa, st, ns),
+                    "pass-1 items")))
         return rc;
     if ((rc = check(launch_item_reps(w.ioffa, nr, w.irepa, st), "pass-1 item reps"))) return rc;
     TileArgs a;
@@ -750,6 +770,7 @@ int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t 
     a.n_r = nr;
     a.pval = w.hval;
     a.pidx = w.hidx;
+    a.isplit = ns;
     const dim3 grid(kItemBlocks);
     rc = p.path == kPathMfma
              ? check(launch_tile_mfma(p.ks, p.c, kTileItems, grid, a, st), "pass 1 (mfma)")
@@ -757,8 +778,8 @@ int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t 
                      "pass 1 (valu)");
     if (rc) return rc;
     const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
-    return check(launch_tau_home(w.hval, p.c, k, (int32_t)m, mode, w.bf.qn, ix->norms_max, ix->d,
-                                 delta, w.taud, st), "k-th neighbour bound");
+    return check(launch_tau_home(w.hval, p.c, ns, k, (int32_t)m, mode, w.bf.qn, ix->norms_max,
+                                 ix->d, delta, w.taud, st), "k-th neighbour bound");
 }
 
 // Exact search, Sec. 5.2: stage 1 (all representative distances), [pass 1

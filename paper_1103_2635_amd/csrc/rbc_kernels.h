@@ -46,9 +46,9 @@ hipError_t launch_prune(const float* DR, int64_t ldd, int32_t m, int32_t nr, int
 // neighbour bound from the nearest list's shortlist, stage-2 item row ranges.
 hipError_t launch_nearest_rep(const float* DR, int64_t ldd, int32_t m, int32_t nr, int32_t* home,
                               hipStream_t st);
-hipError_t launch_tau_home(const float* hval, int32_t c, int32_t k, int32_t m, int32_t mode,
-                           const float* qn, const uint32_t* xmax_bits, int32_t d, double delta,
-                           float* taud, hipStream_t st);
+hipError_t launch_tau_home(const float* hval, int32_t c, int32_t nsplit, int32_t k, int32_t m,
+                           int32_t mode, const float* qn, const uint32_t* xmax_bits, int32_t d,
+                           double delta, float* taud, hipStream_t st);
 hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, const int32_t* ioff,
                             const int32_t* roff, const int32_t* qlist, int32_t isize,
                             const int32_t* list_off, const int32_t* lsorted, const float* own,
@@ -78,7 +78,7 @@ hipError_t launch_oneshot_sort(const float* X, int64_t ldx, int32_t d, int32_t m
                                OneShotWork& w, int32_t* lists, double* psi, hipStream_t st);
 // ioff[r] = items of representative r from query offsets roff, scanned; ioff[nr] = total.
 hipError_t launch_items_from_offsets(const int32_t* roff, int32_t nr, int32_t isize,
-                                     int32_t* ioff, hipStream_t st);
+                                     int32_t* ioff, hipStream_t st, int32_t mult = 1);
 hipError_t launch_list_offsets(int32_t* off, int32_t nr, int32_t s, hipStream_t st);
 // psi_r from the own-sorted lists (float64 re-score of the screened rows).
 hipError_t launch_psi_own(const float* Xp, int64_t ld, int32_t d, int32_t metric, const float* own,

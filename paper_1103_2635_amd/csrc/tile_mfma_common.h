@@ -246,7 +246,12 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         const int item = __builtin_amdgcn_readfirstlane(__shfl(ticket, 0));
         if (item >= total) break;
         const int r = a.irep ? __builtin_amdgcn_readfirstlane(a.irep[item]) : item_rep(a, item);
-        const int q_begin = a.roff[r] + (item - a.ioff[r]) * kWave;
+        int chunk = item - a.ioff[r], split = 0;
+        if (a.isplit > 1) {
+            split = chunk % a.isplit;
+            chunk /= a.isplit;
+        }
+        const int q_begin = a.roff[r] + chunk * kWave;
         const int q_end = a.roff[r + 1];
         typename P::QFrag qf[4][P::kBlocks];
         int qrow[4];
@@ -265,14 +270,18 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         if (a.irows) {
             r0 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item]);
             r1 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item + 1]);
+        } else if (a.isplit > 1) {
+            const int64_t len = r1 - r0;
+            r1 = r0 + (int)(len * (split + 1) / a.isplit);
+            r0 = r0 + (int)(len * split / a.isplit);
         }
         // next ticket: issued after this item's metadata loads (memory
         // counters retire in issue order), consumed at the next iteration
         if (lane == 0) ticket = atomicAdd(a.item_queue, 1);
         if (r0 < r1) scan_rows<P, C>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
         if (valid) {
-            const int64_t pair =
-                a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r] : (int64_t)q;
+            const int64_t pair = a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r]
+                                         : (int64_t)q * (a.isplit > 1 ? a.isplit : 1) + split;
             top.store(a.pval + pair * C, a.pidx + pair * C);
         }
         if (a.stats && lane == 0) {
