@@ -59,6 +59,10 @@ def profiled_traffic(kernel):
     return None
 
 
+def _progress(what):
+    print(json.dumps({"progress": what}), file=sys.stderr, flush=True)
+
+
 def _timed(fn, steps, warmup, sync):
     for _ in range(warmup):
         fn()
@@ -97,8 +101,8 @@ def main():
                     help="run one 256 MiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the build has no multi-GPU path (the design for "
-              "sharding by representative is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (sharding the "
+              "lists by representative is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -245,6 +249,7 @@ def main():
                              n, t_build, samp, m, t_search, m)}
 
     serving = run_serving(rbc, torch, dev) if args.serving else None
+    _progress("optional sections")
     configs = run_configs(rbc, torch, dev) if args.configs else None
     sweep = run_sweeps(rbc, torch, dev, Xd, Qd, w, reps) if args.sweep else None
     rng_line = run_range(rbc, torch, dev, Xd, Qd, w, reps) if args.range else None
@@ -318,6 +323,7 @@ def run_sweeps(rbc, torch, dev, Xd, Qd, w, reps):
     o = (torch.empty((m, 1), dtype=torch.int64, device=dev),
          torch.empty((m, 1), dtype=torch.float32, device=dev))
     eps_rows = []
+    _progress("sweep eps")
     for eps in (0.0, 0.1, 0.25, 0.5, 1.0, 2.0):
         ms = _timed(lambda: rbc.rbc_search(ix, Qd, 1, out=o, workspace=ws, prune_eps=eps), 5, 2,
                     sync)
@@ -335,6 +341,7 @@ def run_sweeps(rbc, torch, dev, Xd, Qd, w, reps):
     out["approximate_eps"] = eps_rows
     nr_rows = []
     for n_r in (250, 500, 1000, 2000, 4000, 8000):
+        _progress("sweep n_r %d" % n_r)
         rr = datagen.random_reps(n, n_r, seed=23)
         b_ms = _timed(lambda: rbc.rbc_build(Xd, n_r, rep_idx=rr).free(), 2, 1, sync)
         ix = rbc.rbc_build(Xd, n_r, rep_idx=rr)
@@ -372,6 +379,7 @@ def run_range(rbc, torch, dev, Xd, Qd, w, reps):
                      device=dev)
     rows = []
     for kth in (1, 20, 200):
+        _progress("range %d" % kth)
         radius = float(np.median(bd[:, kth - 1]))
         holder = {}
 
@@ -525,6 +533,7 @@ def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32", "bf16")):
             return rbc.rbc_search_workspace_size(ix, m, k, precision=prec)
 
         res = {}
+        _progress("serving %s" % prec)
         # saturation: every request of a trace arrives at once
         t, sizes, ks, offs = datagen.arrival_trace("sub12", 1.0, n_requests, pool.shape[0])
         ex = GpuExecutor(pool, search, ws_fn, 4, max_batch=4096, max_k=10)
@@ -541,6 +550,7 @@ def run_serving(rbc, torch, dev, n_requests=2000, precisions=("fp32", "bf16")):
         res["saturation_qps"] = round(sat["qps"], 1)
         mean_size = float(np.mean(sizes))
         for frac in (0.3, 0.6, 0.9):
+            _progress("serving %s load %.1f" % (prec, frac))
             rate = frac * sat["qps"] / mean_size
             tt, _, _, _ = datagen.arrival_trace("sub12", rate, n_requests, pool.shape[0])
             st = run(tt)

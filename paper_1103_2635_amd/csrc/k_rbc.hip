@@ -748,12 +748,13 @@ hipError_t launch_tau_home(const float* hval, int32_t c, int32_t nsplit, int32_t
 // [max(0, rho~/(1 + rel) - t) (1 - rel), (rho~/(1 - rel) + t) (1 + rel)]; a
 // list sorted by own (lsorted[r]) keeps those rows in one run, and the item
 // scans the run covering all of its queries: irows[2 i], irows[2 i + 1].
-// Unsorted lists are scanned whole.  One wavefront per item, grid-stride.
+// Unsorted lists are scanned whole.  taud null: every query has the bound
+// tconst (a range search radius).  One wavefront per item, grid-stride.
 __global__ __launch_bounds__(256) void item_rows_kernel(
     const int32_t* item_total, const int32_t* irep, const int32_t* ioff, const int32_t* roff,
     const int32_t* qlist, int32_t isize, const int32_t* list_off, const int32_t* lsorted,
-    const float* own, const float* DR, int64_t ldd, const float* taud, double rel,
-    int32_t* irows) {
+    const float* own, const float* DR, int64_t ldd, const float* taud, double tconst,
+    double rel, int32_t* irows) {
     const int lane = threadIdx.x & 63;
     const int total = *item_total;
     const int nwave = gridDim.x * 4;
@@ -768,7 +769,7 @@ __global__ __launch_bounds__(256) void item_rows_kernel(
             for (int p = q_begin + lane; p < q_end; p += 64) {
                 const int q = qlist[p];
                 const double rq = (double)DR[(int64_t)q * ldd + r];
-                const double t = (double)taud[q];
+                const double t = taud ? (double)taud[q] : tconst;
                 double l = (rq / (1.0 + rel) - t) * (1.0 - rel);
                 double h = (rq / (1.0 - rel) + t) * (1.0 + rel);
                 if (!(l > 0.0)) l = 0.0;          // also NaN
@@ -805,10 +806,11 @@ __global__ __launch_bounds__(256) void item_rows_kernel(
 hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, const int32_t* ioff,
                             const int32_t* roff, const int32_t* qlist, int32_t isize,
                             const int32_t* list_off, const int32_t* lsorted, const float* own,
-                            const float* DR, int64_t ldd, const float* taud, double rel,
-                            int32_t* irows, hipStream_t st) {
+                            const float* DR, int64_t ldd, const float* taud, double tconst,
+                            double rel, int32_t* irows, hipStream_t st) {
     hipLaunchKernelGGL(item_rows_kernel, dim3(1024), dim3(256), 0, st, item_total, irep, ioff,
-                       roff, qlist, isize, list_off, lsorted, own, DR, ldd, taud, rel, irows);
+                       roff, qlist, isize, list_off, lsorted, own, DR, ldd, taud, tconst, rel,
+                       irows);
     return hipGetLastError();
 }
 

@@ -218,7 +218,11 @@ __global__ __launch_bounds__(256, 2) void tile_valu_range(TileArgs a) {
         f4 qv[F4];
         valu_load_q<KS>(qv, a.Q, a.ldq, a.d, q);
         const float* qp = a.Q + (int64_t)q * a.ldq;
-        const int r0 = a.list_off[r], r1 = a.list_off[r + 1];
+        int r0 = a.list_off[r], r1 = a.list_off[r + 1];
+        if (a.irows) {  // the same entries for the whole workgroup
+            r0 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item]);
+            r1 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item + 1]);
+        }
         int hits = 0;
         for (int base = r0; base < r1; base += kRowsValu) {
             __syncthreads();

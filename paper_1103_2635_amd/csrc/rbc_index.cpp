@@ -841,7 +841,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
         if (p.two_pass &&
             (rc = check(launch_item_rows(w.ioff + nr, w.irep, w.ioff, w.roff, w.qlist, isize,
                                          ix->list_off, ix->lsorted, ix->own, w.DR, ldd, w.taud,
-                                         2.0 * delta, w.irows, st), "item rows")))
+                                         0.0, 2.0 * delta, w.irows, st), "item rows")))
             return rc;
         if (p.path == kPathLowp) {
             const rbc_index::Quant& qc = ix->quant[p.prec];
@@ -920,7 +920,8 @@ struct RangeWork {
     int32_t* ioff = nullptr;
     int32_t* qlist = nullptr;
     int32_t* irep = nullptr;
-    int32_t* cnt = nullptr;  // m + 1
+    int32_t* irows = nullptr;  // 2 per item: the run of its list within the radius
+    int32_t* cnt = nullptr;    // m + 1
 };
 
 struct RangePlan {
@@ -955,6 +956,7 @@ void carve_range(const rbc_index* ix, const RangePlan& rp, int64_t m, Carver& cv
     w->ioff = cv.take<int32_t>(nr + 1);
     w->qlist = cv.take<int32_t>(m * nr);
     w->irep = cv.take<int32_t>(m * nr / kTileQ + nr + 1);
+    w->irows = cv.take<int32_t>(2 * (m * nr / kTileQ + nr + 1));
     w->cnt = cv.take<int32_t>(m + 1);
 }
 
@@ -1009,7 +1011,17 @@ int range_pass(const rbc_index* ix, const RangePlan& rp, const float* Q, int64_t
         if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, kTileQ, w.roff, w.ioff,
                                         w.qlist, st), "work list")))
             return rc;
+        // queries of a list in order of rho(q, r); each item then scans the run
+        // of its list (sorted by the distance to r) where abs(rho(x, r) -
+        // rho(q, r)) <= radius for one of its queries (triangle inequality)
+        if ((rc = check(launch_seg_sort(w.roff, nr, w.qlist, w.DR, ldd, nullptr, st),
+                        "order queries")))
+            return rc;
         if ((rc = check(launch_item_reps(w.ioff, nr, w.irep, st), "item reps"))) return rc;
+        if ((rc = check(launch_item_rows(w.ioff + nr, w.irep, w.ioff, w.roff, w.qlist, kTileQ,
+                                         ix->list_off, ix->lsorted, ix->own, w.DR, ldd, nullptr,
+                                         radius, 2.0 * delta, w.irows, st), "item rows")))
+            return rc;
     }
     TileArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -1028,6 +1040,7 @@ int range_pass(const rbc_index* ix, const RangePlan& rp, const float* Q, int64_t
     a.qlist = w.qlist;
     a.list_off = ix->list_off;
     a.n_r = nr;
+    a.irows = w.irows;
     a.range_fill = fill;
     a.range_radius = radius;
     a.range_cnt = w.cnt;

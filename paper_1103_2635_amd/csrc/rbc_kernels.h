@@ -52,8 +52,8 @@ hipError_t launch_tau_home(const float* hval, int32_t c, int32_t nsplit, int32_t
 hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, const int32_t* ioff,
                             const int32_t* roff, const int32_t* qlist, int32_t isize,
                             const int32_t* list_off, const int32_t* lsorted, const float* own,
-                            const float* DR, int64_t ldd, const float* taud, double rel,
-                            int32_t* irows, hipStream_t st);
+                            const float* DR, int64_t ldd, const float* taud, double tconst,
+                            double rel, int32_t* irows, hipStream_t st);
 hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
                                  hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.
