@@ -61,6 +61,13 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_ite
     tile_items_body<Fp32Policy<KS>, C>(a, tbuf[threadIdx.x >> 6]);
 }
 
+// Pass 1 of the two-pass search: the same item body over the nearest lists.
+template <int KS, int C>
+__global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_home(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
+    tile_items_body<Fp32Policy<KS>, C>(a, tbuf[threadIdx.x >> 6]);
+}
+
 template <int KS>
 __global__ __launch_bounds__(256, 2) void tile_l2_mfma_all(TileArgs a) {
     tile_all_body<Fp32Policy<KS>>(a);
@@ -70,6 +77,8 @@ template <int KS, int C>
 static hipError_t launch_c(int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
     if (mode == kTileItems)
         hipLaunchKernelGGL((tile_l2_mfma_items<KS, C>), grid, dim3(256), 0, st, a);
+    else if (mode == kTileHome)
+        hipLaunchKernelGGL((tile_l2_mfma_home<KS, C>), grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((tile_l2_mfma<KS, C>), grid, dim3(256), 0, st, a);
     return hipGetLastError();

@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256, 2) void tile_valu_range(TileArgs a) {
 
 template <int METRIC, int C>
 static hipError_t launch_c(int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (mode == kTileItems)
+    if (mode == kTileItems || mode == kTileHome)
         hipLaunchKernelGGL((tile_valu_items<METRIC, RBC_KS, C>), grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((tile_valu<METRIC, RBC_KS, C>), grid, dim3(256), 0, st, a);

@@ -25,6 +25,8 @@ constexpr int kTileBF = 0;     // partial shortlists per (split, query)
 constexpr int kTileItems = 1;  // persistent (representative, query chunk) items
 constexpr int kTileAll = 2;    // every value written to pval[q * ldo + row]
 constexpr int kTileRange = 3;  // range search items: count, or write, the rows within a radius
+constexpr int kTileHome = 4;   // item mode for pass 1 of the two-pass search (a kernel of its
+                               // own on the matrix path, so profiles tell the passes apart)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 

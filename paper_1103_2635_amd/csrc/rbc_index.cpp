@@ -773,8 +773,8 @@ int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t 
     a.isplit = ns;
     const dim3 grid(kItemBlocks);
     rc = p.path == kPathMfma
-             ? check(launch_tile_mfma(p.ks, p.c, kTileItems, grid, a, st), "pass 1 (mfma)")
-             : check(launch_tile_valu(p.metric, p.ks, p.c, kTileItems, grid, a, st),
+             ? check(launch_tile_mfma(p.ks, p.c, kTileHome, grid, a, st), "pass 1 (mfma)")
+             : check(launch_tile_valu(p.metric, p.ks, p.c, kTileHome, grid, a, st),
                      "pass 1 (valu)");
     if (rc) return rc;
     const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
