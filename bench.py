@@ -179,6 +179,8 @@ def main():
     st = stats.cpu().numpy()
     cand = int(st[rbc.STAT_CAND])
     pairs = int(st[rbc.STAT_PAIRS])
+    items = int(st[rbc.STAT_ITEMS])
+    slots = int(st[rbc.STAT_SLOTS])
 
     # ---- brute force on the same batch, with its tile timed by the library
     rbc.timer_enable(True)
@@ -280,6 +282,9 @@ def main():
         "candidates_per_query": round(cand / m, 1),
         "candidate_fraction": round(cand / (m * n), 4),
         "pairs_scored_per_query": round(pairs / m, 1),
+        "stage2_items": items,
+        "stage2_rows_per_item": round(slots / 64 / max(items, 1), 1),
+        "stage2_slot_use": round(pairs / max(slots, 1), 4),
         "fallback_queries": int(st[rbc.STAT_FALLBACK]),
         "kernel_ms_per_step": {kn: round(v[0] / args.steps, 4) for kn, v in kernel_ms.items()},
         "roofline": roofline,

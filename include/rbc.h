@@ -85,6 +85,10 @@ typedef enum {
 #define RBC_STAT_CAND       4  /* (query, point) pairs inside kept lists */
 #define RBC_STAT_CASCADE    5  /* low precision: queries whose certificate failed and that the
                                   float32 tile re-ranked over all rows */
+#define RBC_STAT_ITEMS      6  /* stage-2 work items (list, query chunk) processed */
+#define RBC_STAT_SLOTS      7  /* (query, point) slots the stage-2 kernel computed, padding
+                                  included: per item its query-slot width times its rows
+                                  rounded up to the kernel's row block */
 
 /* rbc_search_opts.flags: search an exact index in one pass (every kept list
  * scanned in full, pruning by gamma_k) instead of the default two passes. */

@@ -22,6 +22,7 @@ EXACT, ONESHOT = 0, 1
 FLAG_ONE_PASS = 1
 STATS_LEN = 8
 STAT_FALLBACK, STAT_NEARTIE, STAT_PAIRS, STAT_LISTS, STAT_CAND, STAT_CASCADE = 0, 1, 2, 3, 4, 5
+STAT_ITEMS, STAT_SLOTS = 6, 7
 
 _METRICS = {"l2": L2, "l1": L1, L2: L2, L1: L1}
 _MODES = {"exact": EXACT, "oneshot": ONESHOT, EXACT: EXACT, ONESHOT: ONESHOT}

@@ -750,11 +750,19 @@ hipError_t launch_tau_home(const float* hval, int32_t c, int32_t nsplit, int32_t
 // scans the run covering all of its queries: irows[2 i], irows[2 i + 1].
 // Unsorted lists are scanned whole.  taud null: every query has the bound
 // tconst (a range search radius).  One wavefront per item, grid-stride.
+// With rec non-null the item's record is written as well (representative,
+// first and end query position, row run, item) and its cost class (queries x
+// 32-row blocks, see item_cost) is counted in hist.
+__device__ __forceinline__ int item_cost(int nq, int lo, int hi) {
+    const int c = (nq * ((hi - lo + 31) >> 5)) >> 3;
+    return c < kCostBuckets - 1 ? c : kCostBuckets - 1;
+}
+
 __global__ __launch_bounds__(256) void item_rows_kernel(
     const int32_t* item_total, const int32_t* irep, const int32_t* ioff, const int32_t* roff,
     const int32_t* qlist, int32_t isize, const int32_t* list_off, const int32_t* lsorted,
     const float* own, const float* DR, int64_t ldd, const float* taud, double tconst,
-    double rel, int32_t* irows) {
+    double rel, int32_t* irows, int32_t* rec, int32_t* hist) {
     const int lane = threadIdx.x & 63;
     const int total = *item_total;
     const int nwave = gridDim.x * 4;
@@ -762,9 +770,9 @@ __global__ __launch_bounds__(256) void item_rows_kernel(
         const int r = irep[item];
         const int b = list_off[r], e = list_off[r + 1];
         int lo = b, hi = e;
+        const int q_begin = roff[r] + (item - ioff[r]) * isize;
+        const int q_end = min(q_begin + isize, roff[r + 1]);
         if (lsorted[r]) {
-            const int q_begin = roff[r] + (item - ioff[r]) * isize;
-            const int q_end = min(q_begin + isize, roff[r + 1]);
             double vlo = RBC_INF_D, vhi = 0.0;
             for (int p = q_begin + lane; p < q_end; p += 64) {
                 const int q = qlist[p];
@@ -799,18 +807,79 @@ __global__ __launch_bounds__(256) void item_rows_kernel(
         if (lane == 0) {
             irows[2 * (int64_t)item] = lo;
             irows[2 * (int64_t)item + 1] = hi;
+            if (rec) {
+                int32_t* o = rec + (int64_t)kItemRec * item;
+                *(int4*)o = make_int4(r, q_begin, q_end, lo);
+                *(int4*)(o + 4) = make_int4(hi, item, 0, 0);
+                atomicAdd(hist + item_cost(q_end - q_begin, lo, hi), 1);
+            }
         }
     }
+}
+
+// hist[c] (items of cost class c) -> first queue position of class c, the
+// classes in descending order (one workgroup).
+__global__ __launch_bounds__(1024) void item_order_scan_kernel(int32_t* hist) {
+    __shared__ int32_t part[1024];
+    constexpr int kPer = kCostBuckets / 1024;
+    const int t = threadIdx.x;
+    // thread t owns classes kCostBuckets - 1 - kPer t - j (descending)
+    int v[kPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        v[j] = hist[kCostBuckets - 1 - kPer * t - j];
+        sum += v[j];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int add = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int base = part[t] - sum;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        hist[kCostBuckets - 1 - kPer * t - j] = base;
+        base += v[j];
+    }
+}
+
+// srec[position] = rec[item], positions taken per cost class (the order
+// inside a class is not fixed; every item writes its own output slots).
+__global__ __launch_bounds__(256) void item_order_scatter_kernel(const int32_t* item_total,
+                                                                 const int32_t* rec,
+                                                                 int32_t* base, int32_t* srec) {
+    const int total = *item_total;
+    for (int item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
+        const int4 a = *(const int4*)(rec + (int64_t)kItemRec * item);
+        const int4 b = *(const int4*)(rec + (int64_t)kItemRec * item + 4);
+        const int pos = atomicAdd(base + item_cost(a.z - a.y, a.w, b.x), 1);
+        *(int4*)(srec + (int64_t)kItemRec * pos) = a;
+        *(int4*)(srec + (int64_t)kItemRec * pos + 4) = b;
+    }
+}
+
+hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int32_t* hist,
+                             int32_t* srec, hipStream_t st) {
+    hipLaunchKernelGGL(item_order_scan_kernel, dim3(1), dim3(1024), 0, st, hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(item_order_scatter_kernel, dim3(256), dim3(256), 0, st, item_total, rec,
+                       hist, srec);
+    return hipGetLastError();
 }
 
 hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, const int32_t* ioff,
                             const int32_t* roff, const int32_t* qlist, int32_t isize,
                             const int32_t* list_off, const int32_t* lsorted, const float* own,
                             const float* DR, int64_t ldd, const float* taud, double tconst,
-                            double rel, int32_t* irows, hipStream_t st) {
+                            double rel, int32_t* irows, hipStream_t st, int32_t* rec,
+                            int32_t* hist) {
     hipLaunchKernelGGL(item_rows_kernel, dim3(1024), dim3(256), 0, st, item_total, irep, ioff,
                        roff, qlist, isize, list_off, lsorted, own, DR, ldd, taud, tconst, rel,
-                       irows);
+                       irows, rec, hist);
     return hipGetLastError();
 }
 

@@ -58,7 +58,10 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma(Til
 template <int KS, int C>
 __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_items(TileArgs a) {
     __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
-    tile_items_body<Fp32Policy<KS>, C>(a, tbuf[threadIdx.x >> 6]);
+    if (a.irec)
+        tile_recs_body<Fp32Policy<KS>, C>(a, tbuf[threadIdx.x >> 6]);
+    else
+        tile_items_body<Fp32Policy<KS>, C>(a, tbuf[threadIdx.x >> 6]);
 }
 
 // Pass 1 of the two-pass search: the same item body over the nearest lists.

@@ -130,8 +130,11 @@ __global__ __launch_bounds__(256, 2) void tile_valu_items(TileArgs a) {
         }
         if (a.stats && threadIdx.x == 0) {
             const int nq = q_end - q_begin < kTileQ ? q_end - q_begin : kTileQ;
-            atomicAdd((unsigned long long*)&a.stats[2],
-                      (unsigned long long)nq * (r1 > r0 ? r1 - r0 : 0));
+            const int nrow = r1 > r0 ? r1 - r0 : 0;
+            atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)nq * nrow);
+            atomicAdd((unsigned long long*)&a.stats[6], 1ull);
+            atomicAdd((unsigned long long*)&a.stats[7],
+                      (unsigned long long)kTileQ * ((nrow + kRowsValu - 1) / kRowsValu * kRowsValu));
         }
     }
 }

@@ -19,6 +19,8 @@ constexpr int kRowsMfma = 32;   // database rows per MFMA step (two 16-row block
 constexpr int kRowsValu = 32;   // database rows per VALU tile
 constexpr int kMaxKS = 8;       // 16-feature slabs held in registers: d <= 128
 constexpr int kExactKCap = 1024;
+constexpr int kItemRec = 8;        // int32 per stage-2 item record
+constexpr int kCostBuckets = 2048; // cost classes of the longest-first item order
 
 // tile launch forms
 constexpr int kTileBF = 0;     // partial shortlists per (split, query)
@@ -57,6 +59,9 @@ struct TileArgs {
     const int32_t* irep;   // item -> representative (null: binary search over ioff)
     const int32_t* irows;  // item mode, optional: item i scans rows irows[2 i] .. irows[2 i + 1]
                            // (a run of its list) instead of the whole list
+    const int32_t* irec;   // item mode, optional (exact pairs only): kItemRec int32 per queue
+                           // position: representative, query range, row run, item (see
+                           // item_rows_kernel); the queue hands the records out in this order
     int32_t isplit;        // item mode without lrank, > 1: each query chunk of a list is
                            // isplit items, item j scanning the j-th of isplit equal row
                            // ranges and leaving its shortlist at pair q * isplit + j

@@ -466,6 +466,9 @@ struct SearchWork {
     int32_t* hidx = nullptr;
     float* taud = nullptr;       // m: bound on the k-th neighbour distance
     int32_t* irows = nullptr;    // 2 per pass-2 item: its row run
+    int32_t* rec = nullptr;      // matrix path: kItemRec per pass-2 item, in item order
+    int32_t* srec = nullptr;     // the same records, longest item first
+    int32_t* chist = nullptr;    // kCostBuckets: items per cost class
 };
 
 int64_t stage1_ld(int64_t nr) { return (nr + 3) / 4 * 4; }
@@ -638,6 +641,11 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         w->hidx = cv.take<int32_t>(m * home_splits(ix) * p.c);
         w->taud = cv.take<float>(m);
         w->irows = cv.take<int32_t>(2 * (m * nr / kWave + nr + 1));
+        if (p.path == kPathMfma) {
+            w->rec = cv.take<int32_t>(kItemRec * (m * nr / kWave + nr + 1));
+            w->srec = cv.take<int32_t>(kItemRec * (m * nr / kWave + nr + 1));
+            w->chist = cv.take<int32_t>(kCostBuckets);
+        }
     }
 }
 
@@ -838,10 +846,17 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                         "order queries")))
             return rc;
         if ((rc = check(launch_item_reps(w.ioff, nr, w.irep, st), "item reps"))) return rc;
+        if (w.rec && (rc = check(launch_fill_i32(w.chist, kCostBuckets, 0, st), "clear costs")))
+            return rc;
         if (p.two_pass &&
             (rc = check(launch_item_rows(w.ioff + nr, w.irep, w.ioff, w.roff, w.qlist, isize,
                                          ix->list_off, ix->lsorted, ix->own, w.DR, ldd, w.taud,
-                                         0.0, 2.0 * delta, w.irows, st), "item rows")))
+                                         0.0, 2.0 * delta, w.irows, st, w.rec, w.chist),
+                        "item rows")))
+            return rc;
+        // longest items first, so the persistent launch ends without a tail
+        if (w.rec && (rc = check(launch_item_order(w.ioff + nr, w.rec, w.chist, w.srec, st),
+                                 "item order")))
             return rc;
         if (p.path == kPathLowp) {
             const rbc_index::Quant& qc = ix->quant[p.prec];
@@ -888,6 +903,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     a.pidx = w.bf.pidx;
     a.stats = stats;
     a.irows = p.two_pass ? w.irows : nullptr;
+    a.irec = w.srec;
     {
         KernelTimer kt("tile_items", st);
         const dim3 grid(kItemBlocks);

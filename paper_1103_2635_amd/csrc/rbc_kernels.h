@@ -53,7 +53,13 @@ hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, cons
                             const int32_t* roff, const int32_t* qlist, int32_t isize,
                             const int32_t* list_off, const int32_t* lsorted, const float* own,
                             const float* DR, int64_t ldd, const float* taud, double tconst,
-                            double rel, int32_t* irows, hipStream_t st);
+                            double rel, int32_t* irows, hipStream_t st, int32_t* rec = nullptr,
+                            int32_t* hist = nullptr);
+// Longest-first order of the stage-2 items: the records rec[0 .. *item_total)
+// written by item_rows_kernel, counted per cost class in hist (kCostBuckets,
+// zeroed before item_rows), copied to srec in descending cost.
+hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int32_t* hist,
+                             int32_t* srec, hipStream_t st);
 hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
                                  hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.
