@@ -291,6 +291,51 @@ void rbc_free(rbc_index* index);
 int rbc_timer_enable(int on);
 int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);
 
+/*
+ * Tile autotuner.  The distance step of BF(Q, X) (Sec. 3) runs on the fp32
+ * matrix cores in one of two tile shapes -- 16x16x4 MFMAs with an LDS
+ * transpose before the per-query comparison, or 32x32x2 MFMAs whose output
+ * already holds one query per lane -- and the grouped stage-2 search of the
+ * exact RBC (Sec. 5.2) is one persistent launch whose workgroup count is
+ * free.  Which is fastest depends on d, the shortlist length and the list
+ * sizes.  Untuned, the library uses the 16x16 shape and 1024 workgroups.
+ *
+ * rbc_autotune_search runs the given rbc_search once untimed and three times
+ * timed (HIP events on hip_stream) under each candidate (2 shapes x 512 /
+ * 1024 / 2048 workgroups), rbc_autotune_bf likewise for bf_search (2
+ * shapes); the fastest is kept, process-wide, for every later call with the
+ * same launch kind, 16-feature slab count (ceil(d / 16)) and shortlist
+ * length.  Arguments are those of rbc_search / bf_search (the outputs are
+ * written by every run; results do not depend on the choice).  `out`
+ * (optional, host) receives the choice and its time.  Both synchronise
+ * hip_stream.  RBC_EUNSUPPORTED when the call runs no fp32 matrix-core
+ * launch (L1, d < 12, low precision, one-shot indexes).  Concurrent tuning
+ * calls are safe but time each other's work.
+ */
+typedef struct rbc_tune_result {
+    int32_t shape;       /* 16 or 32 */
+    int32_t blocks;      /* persistent workgroups (stage-2 launch; bf: unused) */
+    float ms;            /* best time of the chosen candidate, whole call */
+    float ms_before;     /* the same for the configuration used before tuning */
+    int32_t candidates;  /* configurations timed */
+} rbc_tune_result;
+
+int rbc_autotune_search(const rbc_index* index, const float* Q, int64_t m, int64_t ldq,
+                        int32_t k, const rbc_search_opts* opts, int64_t* out_idx,
+                        float* out_dist, void* workspace, size_t ws_bytes, void* hip_stream,
+                        rbc_tune_result* out);
+int rbc_autotune_bf(const float* Q, int64_t m, int64_t ldq, const float* X, int64_t n,
+                    int64_t ldx, int32_t d, int32_t metric, int32_t k,
+                    const rbc_search_opts* opts, int64_t* out_idx, float* out_dist,
+                    void* workspace, size_t ws_bytes, void* hip_stream, rbc_tune_result* out);
+/* Pin a choice by hand: kind 0 = bf_search (and the float32 cascade and
+ * the exact-index fallback tile), 1 = rbc_search stage 2; d and shortlist
+ * (4, 8, 16, 32 or 64) select the entry as above; shape 16 or 32; blocks
+ * the stage-2 workgroup count.  RBC_EINVAL on values out of range. */
+int rbc_autotune_set(int32_t kind, int32_t d, int32_t shortlist, int32_t shape, int32_t blocks);
+/* Forget every tuned choice (later calls use the fixed rule). */
+void rbc_autotune_clear(void);
+
 /* rbc_last_error -- message for the last non-OK return on this thread. */
 const char* rbc_last_error(void);
 

@@ -46,6 +46,11 @@ class BuildParams(ctypes.Structure):
                 ("reserved", _I32)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("shape", _I32), ("blocks", _I32), ("ms", ctypes.c_float),
+                ("ms_before", ctypes.c_float), ("candidates", _I32)]
+
+
 class RbcError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("librbc status %d: %s" % (status, msg))
@@ -81,6 +86,13 @@ def lib():
         L.rbc_index_export_order.argtypes = [_P, _P, _P]
         L.rbc_free.argtypes = [_P]
         L.rbc_free.restype = None
+        L.rbc_autotune_search.argtypes = [_P, _P, _I64, _I64, _I32, _P, _P, _P, _P, _SZ, _P,
+                                          ctypes.POINTER(TuneResult)]
+        L.rbc_autotune_bf.argtypes = [_P, _I64, _I64, _P, _I64, _I64, _I32, _I32, _I32, _P, _P,
+                                      _P, _P, _SZ, _P, ctypes.POINTER(TuneResult)]
+        L.rbc_autotune_set.argtypes = [_I32, _I32, _I32, _I32, _I32]
+        L.rbc_autotune_clear.argtypes = []
+        L.rbc_autotune_clear.restype = None
         L.rbc_timer_enable.argtypes = [ctypes.c_int]
         L.rbc_timer_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(_I64)]
@@ -321,6 +333,61 @@ def rbc_range_search(index, Q, radius, workspace=None):
                                   off.data_ptr(), idx.data_ptr(), dist.data_ptr(),
                                   workspace.data_ptr(), workspace.numel(), _stream_ptr(Q)))
     return off, idx[:total], dist[:total]
+
+
+def _tune_dict(r):
+    return {"shape": r.shape, "blocks": r.blocks, "ms": r.ms, "ms_before": r.ms_before,
+            "candidates": r.candidates}
+
+
+def autotune_search(index, Q, k, **kw):
+    """Time the tile shapes and stage-2 grid sizes of rbc_search(index, Q, k)
+    and keep the fastest for later calls; returns the choice and its time."""
+    _mat(Q, "Q")
+    m = Q.shape[0]
+    o = _opts(**kw)
+    sz = _SZ()
+    _check(lib().rbc_search_workspace_size(index.handle, m, Q.stride(0), k, ctypes.byref(o),
+                                           ctypes.byref(sz)))
+    ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=Q.device)
+    idx = torch.empty((m, k), dtype=torch.int64, device=Q.device)
+    dist = torch.empty((m, k), dtype=torch.float32, device=Q.device)
+    r = TuneResult()
+    _check(lib().rbc_autotune_search(index.handle, Q.data_ptr(), m, Q.stride(0), k,
+                                     ctypes.byref(o), idx.data_ptr(), dist.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), _stream_ptr(Q), ctypes.byref(r)))
+    return _tune_dict(r)
+
+
+def autotune_bf(Q, X, k, metric="l2", **kw):
+    """Time the tile shapes of bf_search(Q, X, k) and keep the fastest."""
+    _mat(Q, "Q")
+    _mat(X, "X")
+    m, d = Q.shape
+    n = X.shape[0]
+    o = _opts(**kw)
+    sz = _SZ()
+    _check(lib().bf_search_workspace_size(m, n, d, Q.stride(0), X.stride(0), _METRICS[metric], k,
+                                          ctypes.byref(o), ctypes.byref(sz)))
+    ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=Q.device)
+    idx = torch.empty((m, k), dtype=torch.int64, device=Q.device)
+    dist = torch.empty((m, k), dtype=torch.float32, device=Q.device)
+    r = TuneResult()
+    _check(lib().rbc_autotune_bf(Q.data_ptr(), m, Q.stride(0), X.data_ptr(), n, X.stride(0), d,
+                                 _METRICS[metric], k, ctypes.byref(o), idx.data_ptr(),
+                                 dist.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(Q),
+                                 ctypes.byref(r)))
+    return _tune_dict(r)
+
+
+def autotune_set(kind, d, shortlist, shape, blocks=1024):
+    """Pin the tile choice of kind "bf" or "search" for (d, shortlist length)."""
+    _check(lib().rbc_autotune_set({"bf": 0, "search": 1}[kind], d, shortlist, shape, blocks))
+
+
+def autotune_clear():
+    """Forget every tuned choice."""
+    lib().rbc_autotune_clear()
 
 
 def timer_enable(on=True):

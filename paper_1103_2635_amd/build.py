@@ -31,7 +31,7 @@ PER_KB = ["k_tile_lowp.hip"]
 # path.  The tile files have no other atomics it would help.
 TILE_FLAGS = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 SINGLE = ["k_util.hip", "k_finalize.hip", "k_rbc.hip", "k_oneshot.hip", "k_quant.hip", "rbc_dispatch.cpp", "rbc_api.cpp",
-          "rbc_index.cpp", "rbc_timer.cpp"]
+          "rbc_index.cpp", "rbc_timer.cpp", "rbc_tune.cpp"]
 
 
 def _units():

@@ -5,6 +5,7 @@
 // MFMAs (k-slot l / 16 each).  Query fragments are -2 q (exact).  The scan,
 // transpose and shortlist are in tile_mfma_common.h.
 #include "tile_mfma_common.h"
+#include "tile_mfma32.h"
 
 #ifndef RBC_KS
 #error "compile with -DRBC_KS=<1..8>"
@@ -71,6 +72,22 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_hom
     tile_items_body<Fp32Policy<KS>, C>(a, tbuf[threadIdx.x >> 6]);
 }
 
+// The 32x32x2 shape (tile_mfma32.h): no LDS, two shortlists per lane.
+template <int KS, int C>
+struct Mfma32Occ {
+    static constexpr int value = (32 * KS + 4 * C + 96 <= 256) ? 2 : 1;
+};
+
+template <int KS, int C>
+__global__ __launch_bounds__(256, (Mfma32Occ<KS, C>::value)) void tile_l2_mfma32(TileArgs a) {
+    tile32_bf_body<KS, C>(a);
+}
+
+template <int KS, int C>
+__global__ __launch_bounds__(256, (Mfma32Occ<KS, C>::value)) void tile_l2_mfma32_items(TileArgs a) {
+    tile32_recs_body<KS, C>(a);
+}
+
 template <int KS>
 __global__ __launch_bounds__(256, 2) void tile_l2_mfma_all(TileArgs a) {
     tile_all_body<Fp32Policy<KS>>(a);
@@ -78,7 +95,11 @@ __global__ __launch_bounds__(256, 2) void tile_l2_mfma_all(TileArgs a) {
 
 template <int KS, int C>
 static hipError_t launch_c(int mode, dim3 grid, const TileArgs& a, hipStream_t st) {
-    if (mode == kTileItems)
+    if (a.shape == kShape32 && mode == kTileBF)
+        hipLaunchKernelGGL((tile_l2_mfma32<KS, C>), grid, dim3(256), 0, st, a);
+    else if (a.shape == kShape32 && mode == kTileItems && a.irec)
+        hipLaunchKernelGGL((tile_l2_mfma32_items<KS, C>), grid, dim3(256), 0, st, a);
+    else if (mode == kTileItems)
         hipLaunchKernelGGL((tile_l2_mfma_items<KS, C>), grid, dim3(256), 0, st, a);
     else if (mode == kTileHome)
         hipLaunchKernelGGL((tile_l2_mfma_home<KS, C>), grid, dim3(256), 0, st, a);

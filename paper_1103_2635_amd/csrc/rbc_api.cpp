@@ -87,6 +87,7 @@ int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int3
         p->ldc = ((int64_t)d + 3) / 4 * 4;
     } else if (metric == RBC_L2 && d >= 12) {
         p->path = kPathMfma;
+        p->shape = tile_choice(kTuneBF, p->ks, p->c).shape;
     } else {
         p->path = kPathValu;
     }
@@ -151,6 +152,7 @@ int run_cascade(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const f
     a.pidx = w.pidx_c;
     a.m_dev = ctr + 1;
     a.dev_blocks = p.casc_blocks;
+    a.shape = tile_choice(kTuneBF, p.ks32, p.c32).shape;
     if ((rc = hip_status(launch_tile_mfma(p.ks32, p.c32, kTileBF, dim3(p.casc_blocks), a, st),
                          "cascade tile")))
         return rc;
@@ -328,6 +330,7 @@ int run_bf(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const float*
     a.pval = w.pval;
     a.pidx = w.pidx;
     a.stats = stats;
+    a.shape = p.shape;
     {
         KernelTimer kt("tile", st);
         const dim3 grid(p.nqblk, p.nsplit);

@@ -30,6 +30,10 @@ constexpr int kTileRange = 3;  // range search items: count, or write, the rows 
 constexpr int kTileHome = 4;   // item mode for pass 1 of the two-pass search (a kernel of its
                                // own on the matrix path, so profiles tell the passes apart)
 
+// shapes of the fp32 matrix-core tile (TileArgs.shape)
+constexpr int kShape16 = 0;  // v_mfma_f32_16x16x4f32, LDS transpose for the comparison
+constexpr int kShape32 = 1;  // v_mfma_f32_32x32x2f32, no transpose (BF and record items)
+
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // One tile launch.  BF mode: grid (query blocks of 256, database splits);
@@ -79,6 +83,7 @@ struct TileArgs {
     int32_t* pidx;         // partial shortlist rows (-1 = no row)
     int64_t ldo;           // kTileAll: row stride of the value matrix
     int64_t* stats;        // optional device counters
+    int32_t shape;         // fp32 matrix tile: kShape16 or kShape32
     // BF mode with a device-side query count (non-null m_dev): the first
     // *m_dev rows of Q are searched by a 1-D grid of dev_blocks workgroups
     // whose (query block, split) layout is derived from the count (dev_split)

@@ -71,6 +71,7 @@ struct BfPlan {
     double prune_eps;     // exact RBC search: pruning bounds divided by (1 + eps)
     bool one_pass;        // RBC_FLAG_ONE_PASS given
     bool two_pass;        // exact RBC search in two passes (set by the index's planner)
+    int shape;            // fp32 matrix tile shape of the BF launch (kShape16 / kShape32)
 };
 
 struct BfWork {
@@ -114,6 +115,16 @@ private:
     hipEvent_t a_ = nullptr, b_ = nullptr;
     bool active_ = false;
 };
+
+// Tile configuration of one fp32 matrix-core launch (rbc_tune.cpp): the
+// tuned choice for (kind, slabs, shortlist length), else the fixed rule.
+constexpr int kTuneBF = 0;     // BF tile (bf_search, cascade, exact-index fallback)
+constexpr int kTuneItems = 1;  // stage 2 of the exact RBC search
+struct TileChoice {
+    int shape = kShape16;
+    int blocks = kItemBlocks;
+};
+TileChoice tile_choice(int kind, int ks, int c);
 
 int make_bf_plan(int64_t m, int64_t n, int32_t d, int64_t ldq, int64_t ldx, int32_t metric,
                  int32_t k, const rbc_search_opts* opts, BfPlan* p);

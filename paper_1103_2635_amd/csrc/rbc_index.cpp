@@ -904,9 +904,11 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     a.stats = stats;
     a.irows = p.two_pass ? w.irows : nullptr;
     a.irec = w.srec;
+    const TileChoice tc = tile_choice(kTuneItems, p.ks, p.c);
+    a.shape = tc.shape;
     {
         KernelTimer kt("tile_items", st);
-        const dim3 grid(kItemBlocks);
+        const dim3 grid(tc.blocks);
         rc = p.path == kPathMfma
                  ? check(launch_tile_mfma(p.ks, p.c, kTileItems, grid, a, st), "stage 2 (mfma)")
                  : check(launch_tile_valu(p.metric, p.ks, p.c, kTileItems, grid, a, st),
@@ -1188,6 +1190,24 @@ int rbc_search(const rbc_index* ix, const float* Q, int64_t m, int64_t ldq, int3
         return set_err(RBC_EHIP, "unexpected exception");
     }
 }
+
+}  // extern "C"
+
+// Tuning key of an rbc_search call (rbc_tune.cpp): kind kTuneItems when the
+// exact search runs its stage 2 on the fp32 matrix tile, -1 otherwise.
+int search_tune_key(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
+                    const rbc_search_opts* opts, int32_t* kind, int32_t* ks, int32_t* c) {
+    int rc = validate_search(ix, m, ldq, k);
+    if (rc) return rc;
+    BfPlan p;
+    if ((rc = search_plan(ix, m > 0 ? m : 1, ldq, k, opts, &p))) return rc;
+    *kind = (ix->mode == RBC_EXACT && p.path == kPathMfma) ? kTuneItems : -1;
+    *ks = p.ks;
+    *c = p.c;
+    return RBC_OK;
+}
+
+extern "C" {
 
 int rbc_range_workspace_size(const rbc_index* ix, int64_t m, int64_t ldq, size_t* bytes) {
     try {
