@@ -137,6 +137,16 @@ def main():
     bf_ws = torch.empty(rbc.bf_search_workspace_size(m, n, d, k, metric), dtype=torch.uint8,
                         device=dev)
 
+    # ---- tile autotuning (library call, before any timing): the stage-2 and
+    # pass-1 configuration of the exact search and the BF tile shape
+    tuning = {}
+    if metric == "l2":
+        _progress("autotune")
+        ix0 = rbc.rbc_build(Xd, w.n_r, metric=metric, rep_idx=reps)
+        tuning["rbc_search"] = rbc.autotune_search(ix0, Qd, k)
+        ix0.free()
+        tuning["bf_search"] = rbc.autotune_bf(Qd, Xd, k, metric)
+
     # ---- the step: build + search
     holder = {}
 
@@ -203,10 +213,14 @@ def main():
     # stage 2 scores, for each work item, its queries against the run of rows
     # of its list that the two-pass bound leaves (pairs); that is the work
     roofline = roof(per_pair * pairs, tile_avg)
-    roofline["traffic"] = (profiled_traffic("void rbc::tile_l2_mfma_items<4, 4>")
+    kname = "tile_valu_items"
+    if metric == "l2":
+        kname = ("tile_l2_mfma32_items" if tuning.get("rbc_search", {}).get("shape") == 32
+                 else "tile_l2_mfma_items")
+    roofline["traffic"] = (profiled_traffic("void rbc::%s<4, 4>" % kname)
                            if (metric, k) == ("l2", 1) else None)
     roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)"
-    roofline["kernel"] = "tile_l2_mfma_items (RBC stage 2)" if metric == "l2" else "tile_valu_items (RBC stage 2)"
+    roofline["kernel"] = kname + " (RBC stage 2)"
     roofline["avg_ms"] = round(tile_avg, 4)
     roofline["algorithmic_units"] = ("2*d per (query, row) pair scored: sum over items of "
                                      "queries x rows of the item's run = %d pairs, %d flops per "
@@ -287,6 +301,7 @@ def main():
         "stage2_slot_use": round(pairs / max(slots, 1), 4),
         "fallback_queries": int(st[rbc.STAT_FALLBACK]),
         "kernel_ms_per_step": {kn: round(v[0] / args.steps, 4) for kn, v in kernel_ms.items()},
+        "tuning": tuning,
         "roofline": roofline,
         "bf_roofline": bf_roof,
         "cpu_baseline": cpu,

@@ -274,7 +274,10 @@ int rbc_index_export(const rbc_index* index, int64_t* rep_idx, double* psi,
  */
 int rbc_index_export_order(const rbc_index* index, float* own, int32_t* sorted);
 
-/* rbc_free -- release an index (NULL is a no-op).  Synchronises the device. */
+/* rbc_free -- release an index (NULL is a no-op).  Synchronises the device.
+ * The index's main device block (everything but optional quantised copies)
+ * is kept, one block per device, for the next rbc_build on that device that
+ * needs at least half of it; a larger freed block replaces a cached one. */
 void rbc_free(rbc_index* index);
 
 /*
@@ -302,8 +305,9 @@ int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);
  *
  * rbc_autotune_search runs the given rbc_search once untimed and three times
  * timed (HIP events on hip_stream) under each candidate (2 shapes x 512 /
- * 1024 / 2048 workgroups), rbc_autotune_bf likewise for bf_search (2
- * shapes); the fastest is kept, process-wide, for every later call with the
+ * 1024 / 2048 workgroups x pass-1 splits by the size rule, 2 or 4),
+ * rbc_autotune_bf likewise for bf_search (2 shapes); the fastest is kept,
+ * process-wide, for every later call with the
  * same launch kind, 16-feature slab count (ceil(d / 16)) and shortlist
  * length.  Arguments are those of rbc_search / bf_search (the outputs are
  * written by every run; results do not depend on the choice).  `out`
@@ -315,6 +319,7 @@ int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);
 typedef struct rbc_tune_result {
     int32_t shape;       /* 16 or 32 */
     int32_t blocks;      /* persistent workgroups (stage-2 launch; bf: unused) */
+    int32_t splits;      /* row ranges per nearest list in pass 1 (0: size rule; bf: unused) */
     float ms;            /* best time of the chosen candidate, whole call */
     float ms_before;     /* the same for the configuration used before tuning */
     int32_t candidates;  /* configurations timed */
@@ -329,10 +334,12 @@ int rbc_autotune_bf(const float* Q, int64_t m, int64_t ldq, const float* X, int6
                     const rbc_search_opts* opts, int64_t* out_idx, float* out_dist,
                     void* workspace, size_t ws_bytes, void* hip_stream, rbc_tune_result* out);
 /* Pin a choice by hand: kind 0 = bf_search (and the float32 cascade and
- * the exact-index fallback tile), 1 = rbc_search stage 2; d and shortlist
- * (4, 8, 16, 32 or 64) select the entry as above; shape 16 or 32; blocks
- * the stage-2 workgroup count.  RBC_EINVAL on values out of range. */
-int rbc_autotune_set(int32_t kind, int32_t d, int32_t shortlist, int32_t shape, int32_t blocks);
+ * the exact-index fallback tile), 1 = rbc_search (stage 2 and pass 1); d and
+ * shortlist (4, 8, 16, 32 or 64) select the entry as above; shape 16 or 32;
+ * blocks the stage-2 workgroup count; splits 0 .. 8 the pass-1 row ranges per
+ * nearest list (0: the size rule).  RBC_EINVAL on values out of range. */
+int rbc_autotune_set(int32_t kind, int32_t d, int32_t shortlist, int32_t shape, int32_t blocks,
+                     int32_t splits);
 /* Forget every tuned choice (later calls use the fixed rule). */
 void rbc_autotune_clear(void);
 

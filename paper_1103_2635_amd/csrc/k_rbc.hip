@@ -687,7 +687,6 @@ hipError_t launch_nearest_rep(const float* DR, int64_t ldd, int32_t m, int32_t n
 // (1 + (d + 2) u)); mode 1 (direct squared l2, relative error <= delta):
 // sqrt(v / (1 - delta)); mode 2 (direct l1): v / (1 - delta); each widened
 // by 1e-6 and rounded up to a float.  +inf when the list has fewer than k rows.
-constexpr int kMaxHomeSplit = 8;
 
 __global__ void tau_home_kernel(const float* hval, int32_t c, int32_t nsplit, int32_t k,
                                 int32_t m, int32_t mode, const float* qn,

@@ -21,6 +21,7 @@ constexpr int kMaxKS = 8;       // 16-feature slabs held in registers: d <= 128
 constexpr int kExactKCap = 1024;
 constexpr int kItemRec = 8;        // int32 per stage-2 item record
 constexpr int kCostBuckets = 2048; // cost classes of the longest-first item order
+constexpr int kMaxHomeSplit = 8;   // row ranges per nearest list in pass 1 of the two-pass search
 
 // tile launch forms
 constexpr int kTileBF = 0;     // partial shortlists per (split, query)

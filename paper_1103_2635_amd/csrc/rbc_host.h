@@ -123,6 +123,7 @@ constexpr int kTuneItems = 1;  // stage 2 of the exact RBC search
 struct TileChoice {
     int shape = kShape16;
     int blocks = kItemBlocks;
+    int splits = 0;  // row ranges per nearest list in pass 1 (0: the size rule)
 };
 TileChoice tile_choice(int kind, int ks, int c);
 

@@ -52,6 +52,9 @@ struct rbc_index {
     std::vector<int64_t> rep_host;
     std::vector<void*> allocs;
     size_t bytes = 0;
+    void* block = nullptr;       // the main allocation (Layout), returned to the block cache
+    size_t block_bytes = 0;
+    int block_dev = 0;
 };
 
 namespace {
@@ -70,10 +73,55 @@ int dev_alloc(rbc_index* ix, T** p, int64_t count) {
     return RBC_OK;
 }
 
+// The main device block of the last freed index, one per device, handed to
+// the next build that fits in it: a rebuild (a new batch of points) then
+// neither frees nor maps a few hundred MB, which costs about 0.4 ms.
+std::mutex g_block_mu;
+std::map<int, std::pair<void*, size_t>> g_block_cache;
+
+int take_block(size_t bytes, void** out, int* dev_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_err(RBC_EHIP, "hipGetDevice failed");
+    *dev_out = dev;
+    {
+        std::lock_guard<std::mutex> lk(g_block_mu);
+        auto it = g_block_cache.find(dev);
+        // reuse a cached block no more than twice the size needed (plus 64 MB)
+        if (it != g_block_cache.end() && it->second.second >= bytes &&
+            it->second.second <= 2 * bytes + ((size_t)64 << 20)) {
+            *out = it->second.first;
+            g_block_cache.erase(it);
+            return RBC_OK;
+        }
+    }
+    if (hipMalloc(out, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(RBC_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    return RBC_OK;
+}
+
+void give_block(void* p, size_t bytes, int dev) {
+    void* drop = p;
+    {
+        std::lock_guard<std::mutex> lk(g_block_mu);
+        auto it = g_block_cache.find(dev);
+        if (it == g_block_cache.end()) {
+            g_block_cache[dev] = {p, bytes};
+            drop = nullptr;
+        } else if (it->second.second < bytes) {
+            drop = it->second.first;
+            it->second = {p, bytes};
+        }
+    }
+    if (drop) (void)hipFree(drop);
+}
+
 void free_index(rbc_index* ix) {
     if (!ix) return;
     (void)hipDeviceSynchronize();
     for (void* p : ix->allocs) (void)hipFree(p);
+    if (ix->block) give_block(ix->block, ix->block_bytes, ix->block_dev);
     delete ix;
 }
 
@@ -109,11 +157,11 @@ struct Layout {
         size_t total = 0;
         for (auto& it : items) total += (it.second + 255) & ~(size_t)255;
         void* base = nullptr;
-        if (hipMalloc(&base, total) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_err(RBC_ENOMEM, "device allocation of %zu bytes failed", total);
-        }
-        ix->allocs.push_back(base);
+        int dev = 0;
+        if (int rc = take_block(total, &base, &dev)) return rc;
+        ix->block = base;
+        ix->block_bytes = total;
+        ix->block_dev = dev;
         ix->bytes += total;
         char* c = (char*)base;
         for (auto& it : items) {
@@ -596,9 +644,11 @@ int search_oneshot(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t
 // Pass 1 of the two-pass search splits each nearest list into this many row
 // ranges (one work item each, about 128 rows or more), so that the few
 // queries of a list are served by several wavefronts.
-int home_splits(const rbc_index* ix) {
+int home_splits(const rbc_index* ix, const BfPlan& p) {
+    const TileChoice tc = tile_choice(kTuneItems, p.ks, p.c);
+    if (tc.splits > 0) return std::min(tc.splits, kMaxHomeSplit);
     const int64_t per_list = ix->rows / std::max<int64_t>(ix->n_r, 1);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(8, per_list / 128));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxHomeSplit, per_list / 128));
 }
 
 void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, SearchWork* w) {
@@ -635,10 +685,11 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         w->qa = cv.take<int32_t>(m);
         w->roffa = cv.take<int32_t>(nr + 1);
         w->ioffa = cv.take<int32_t>(nr + 1);
-        w->irepa = cv.take<int32_t>((m / kWave + nr + 1) * home_splits(ix));
+        // pass-1 items hold 16 queries (matrix path) or 256 (vector path)
+        w->irepa = cv.take<int32_t>((m / 16 + nr + 1) * kMaxHomeSplit);
         w->csa = cv.take<int32_t>(csort_scratch(m, (int32_t)nr));
-        w->hval = cv.take<float>(m * home_splits(ix) * p.c);
-        w->hidx = cv.take<int32_t>(m * home_splits(ix) * p.c);
+        w->hval = cv.take<float>(m * kMaxHomeSplit * p.c);
+        w->hidx = cv.take<int32_t>(m * kMaxHomeSplit * p.c);
         w->taud = cv.take<float>(m);
         w->irows = cv.take<int32_t>(2 * (m * nr / kWave + nr + 1));
         if (p.path == kPathMfma) {
@@ -746,14 +797,16 @@ int search_exact_lowp(const rbc_index* ix, const BfPlan& p, const float* Q, int6
 int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t ldqk, int64_t m,
                  int32_t k, SearchWork& w, double delta, int64_t ldd, hipStream_t st) {
     const int32_t nr = (int32_t)ix->n_r;
-    const int32_t isize = p.path == kPathValu ? kTileQ : kWave;
+    // items of 16 queries on the matrix path (tile_l2_mfma_home), 256 on the
+    // vector path
+    const int32_t isize = p.path == kPathValu ? kTileQ : 16;
     KernelTimer kt("pass1", st);
     int rc;
     if ((rc = check(launch_nearest_rep(w.DR, ldd, (int32_t)m, nr, w.home, st), "nearest rep")))
         return rc;
     if ((rc = check(launch_csort(w.home, m, nr, w.csa, w.qa, w.roffa, st), "group by home")))
         return rc;
-    const int ns = home_splits(ix);
+    const int ns = home_splits(ix, p);
     if ((rc = check(launch_items_from_offsets(w.roffa, nr, isize, w.ioffa, st, ns),
                     "pass-1 items")))
         return rc;

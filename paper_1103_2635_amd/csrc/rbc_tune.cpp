@@ -1,7 +1,8 @@
 // rbc_tune.cpp -- the tile autotuner: which fp32 matrix-core tile shape
-// (16x16x4 with an LDS transpose, or 32x32x2 without) and, for the
-// persistent stage-2 launch of the exact search, how many workgroups, per
-// (launch kind, 16-feature slab count, shortlist length).
+// (16x16x4 with an LDS transpose, or 32x32x2 without) and, for the exact
+// search, how many workgroups the persistent stage-2 launch has and into how
+// many row ranges pass 1 splits each nearest list, per (launch kind,
+// 16-feature slab count, shortlist length).
 //
 // Until a configuration is tuned the library uses the 16x16 shape and
 // kItemBlocks workgroups (on the 10^6 x 64 subspace workload the 16x16 shape
@@ -89,7 +90,8 @@ int pick(int kind, int ks, int c, const std::vector<Candidate>& res, rbc_tune_re
     float def_ms = -1.f;
     for (const Candidate& r : res) {
         if (!best || r.ms < best->ms) best = &r;
-        if (r.t.shape == def.shape && r.t.blocks == def.blocks) def_ms = r.ms;
+        if (r.t.shape == def.shape && r.t.blocks == def.blocks && r.t.splits == def.splits)
+            def_ms = r.ms;
     }
     if (!best) return set_err(RBC_EINVAL, "no candidate configuration");
     {
@@ -99,6 +101,7 @@ int pick(int kind, int ks, int c, const std::vector<Candidate>& res, rbc_tune_re
     if (out) {
         out->shape = best->t.shape == kShape32 ? 32 : 16;
         out->blocks = best->t.blocks;
+        out->splits = best->t.splits;
         out->ms = best->ms;
         out->ms_before = def_ms;
         out->candidates = (int32_t)res.size();
@@ -142,12 +145,14 @@ int rbc_autotune_search(const rbc_index* ix, const float* Q, int64_t m, int64_t 
                                      "this search runs no tunable matrix-core launch");
         std::vector<TileChoice> cands;
         for (int sh : {kShape16, kShape32})
-            for (int blocks : {kItemBlocks / 2, kItemBlocks, 2 * kItemBlocks}) {
-                TileChoice t;
-                t.shape = sh;
-                t.blocks = blocks;
-                cands.push_back(t);
-            }
+            for (int blocks : {kItemBlocks / 2, kItemBlocks, 2 * kItemBlocks})
+                for (int splits : {0, 2, 4}) {
+                    TileChoice t;
+                    t.shape = sh;
+                    t.blocks = blocks;
+                    t.splits = splits;
+                    cands.push_back(t);
+                }
         std::vector<Candidate> res;
         hipStream_t st = (hipStream_t)hip_stream;
         rc = time_choices(cands, st, 3, [&]() {
@@ -186,16 +191,19 @@ int rbc_autotune_bf(const float* Q, int64_t m, int64_t ldq, const float* X, int6
 }
 
 int rbc_autotune_set(int32_t kind, int32_t d, int32_t shortlist, int32_t shape,
-                     int32_t blocks) {
+                     int32_t blocks, int32_t splits) {
     if (kind != 0 && kind != 1) return set_err(RBC_EINVAL, "kind must be 0 (bf) or 1 (search)");
     if (d < 1 || d > 16 * kMaxKS) return set_err(RBC_EINVAL, "d must be in 1 .. %d", 16 * kMaxKS);
     if (shortlist != 4 && shortlist != 8 && shortlist != 16 && shortlist != 32 && shortlist != 64)
         return set_err(RBC_EINVAL, "shortlist must be 4, 8, 16, 32 or 64");
     if (shape != 16 && shape != 32) return set_err(RBC_EINVAL, "shape must be 16 or 32");
     if (blocks < 1 || blocks > 65536) return set_err(RBC_EINVAL, "blocks must be in 1 .. 65536");
+    if (splits < 0 || splits > kMaxHomeSplit)
+        return set_err(RBC_EINVAL, "splits must be in 0 .. %d", kMaxHomeSplit);
     TileChoice t;
     t.shape = shape == 32 ? kShape32 : kShape16;
     t.blocks = blocks;
+    t.splits = splits;
     std::lock_guard<std::mutex> lk(g_mu);
     g_table[std::make_tuple(kind == 0 ? kTuneBF : kTuneItems, (d + 15) / 16, shortlist)] = t;
     return RBC_OK;

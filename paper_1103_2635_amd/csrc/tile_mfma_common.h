@@ -47,11 +47,11 @@ __device__ __forceinline__ void load_xfrags(typename P::XFrag (&xa)[2][P::kBlock
     }
 }
 
-template <class P>
-__device__ __forceinline__ void load_qfrags(typename P::QFrag (&qf)[4][P::kBlocks],
-                                            const TileArgs& a, const int (&qrow)[4], int g) {
+template <class P, int QB>
+__device__ __forceinline__ void load_qfrags(typename P::QFrag (&qf)[QB][P::kBlocks],
+                                            const TileArgs& a, const int (&qrow)[QB], int g) {
 #pragma unroll
-    for (int qb = 0; qb < 4; ++qb)
+    for (int qb = 0; qb < QB; ++qb)
 #pragma unroll
         for (int f = 0; f < P::kBlocks; ++f) P::load_q(qf[qb][f], a, qrow[qb], f, g);
 }
@@ -68,10 +68,10 @@ __device__ __forceinline__ void load_norms(f4 (&nr)[2], const float* xn, int bas
         }
 }
 
-// The 32 x 64 values of rows [base, base + 32): acc[rb][qb][i] is row
+// The 32 x 16 QB values of rows [base, base + 32): acc[rb][qb][i] is row
 // base + 16 rb + 4 g + i, query 16 qb + c16 (+inf beyond r1).
-template <class P>
-__device__ __forceinline__ void tile_step(f4 (&acc)[2][4], const typename P::QFrag (&qf)[4][P::kBlocks],
+template <class P, int QB>
+__device__ __forceinline__ void tile_step(f4 (&acc)[2][QB], const typename P::QFrag (&qf)[QB][P::kBlocks],
                                           const typename P::XFrag (&xa)[2][P::kBlocks],
                                           const f4 (&nr)[2], int base, int r1, int g) {
 #pragma unroll
@@ -83,41 +83,41 @@ __device__ __forceinline__ void tile_step(f4 (&acc)[2][4], const typename P::QFr
             nv[i] = row < r1 ? nr[rb][i] : RBC_INF;
         }
 #pragma unroll
-        for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = P::mma(xa[rb][0], qf[qb][0], nv);
+        for (int qb = 0; qb < QB; ++qb) acc[rb][qb] = P::mma(xa[rb][0], qf[qb][0], nv);
     }
 #pragma unroll
     for (int f = 1; f < P::kBlocks; ++f)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int qb = 0; qb < 4; ++qb) acc[rb][qb] = P::mma(xa[rb][f], qf[qb][f], acc[rb][qb]);
+            for (int qb = 0; qb < QB; ++qb) acc[rb][qb] = P::mma(xa[rb][f], qf[qb][f], acc[rb][qb]);
 }
 
 // Each lane keeps, for the four queries whose values it holds in the MFMA
 // layout (16 qb + c16), a copy of their shortlist bound (-inf for lanes
 // without a query, which never insert).
-template <int C>
-__device__ __forceinline__ void refresh_bounds(float (&wq)[4], const TopC<C>& top, bool act,
+template <int C, int QB>
+__device__ __forceinline__ void refresh_bounds(float (&wq)[QB], const TopC<C>& top, bool act,
                                                int c16) {
     const float w = act ? top.worst() : -RBC_INF;
 #pragma unroll
-    for (int qb = 0; qb < 4; ++qb) wq[qb] = __shfl(w, 16 * qb + c16);
+    for (int qb = 0; qb < QB; ++qb) wq[qb] = __shfl(w, 16 * qb + c16);
 }
 
 // One 32-row block: the values, the min-filter, and (only when some lane
 // may insert) the transpose and the pushes.
-template <class P, int C>
-__device__ __forceinline__ void scan_block(const typename P::QFrag (&qf)[4][P::kBlocks],
+template <class P, int C, int QB>
+__device__ __forceinline__ void scan_block(const typename P::QFrag (&qf)[QB][P::kBlocks],
                                            const typename P::XFrag (&x)[2][P::kBlocks],
                                            const f4 (&nr)[2], int base, int r1, bool act,
-                                           TopC<C>& top, float (&wq)[4], float* tb, int lane) {
+                                           TopC<C>& top, float (&wq)[QB], float* tb, int lane) {
     const int g = lane >> 4;
     const int c16 = lane & 15;
-    f4 acc[2][4];
-    tile_step<P>(acc, qf, x, nr, base, r1, g);
+    f4 acc[2][QB];
+    tile_step<P, QB>(acc, qf, x, nr, base, r1, g);
     bool need = false;
 #pragma unroll
-    for (int qb = 0; qb < 4; ++qb) {
+    for (int qb = 0; qb < QB; ++qb) {
         const float m0 = fminf(fminf(acc[0][qb][0], acc[0][qb][1]), fminf(acc[0][qb][2], acc[0][qb][3]));
         const float m1 = fminf(fminf(acc[1][qb][0], acc[1][qb][1]), fminf(acc[1][qb][2], acc[1][qb][3]));
         need |= fminf(m0, m1) < wq[qb];
@@ -128,7 +128,7 @@ __device__ __forceinline__ void scan_block(const typename P::QFrag (&qf)[4][P::k
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int qb = 0; qb < 4; ++qb)
+            for (int qb = 0; qb < QB; ++qb)
                 *(f4*)(tb + (16 * qb + c16) * kTStride + 16 * rb + 4 * g) = acc[rb][qb];
         wave_lds_sync();
         f4 vals[8];
@@ -140,7 +140,7 @@ __device__ __forceinline__ void scan_block(const typename P::QFrag (&qf)[4][P::k
 #pragma unroll
                 for (int i = 0; i < 4; ++i) top.push(vals[t][i], base + 4 * t + i);
         }
-        refresh_bounds<C>(wq, top, act, c16);
+        refresh_bounds<C, QB>(wq, top, act, c16);
     }
 }
 
@@ -152,14 +152,14 @@ __device__ __forceinline__ void scan_block(const typename P::QFrag (&qf)[4][P::k
 // shortlists, are those of the plain scan).  Two fragment buffers alternate:
 // while one block is scored, the next block's fragments and norms load into
 // the other, issued before the block's MFMAs, with no register copies.
-template <class P, int C>
-__device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[4][P::kBlocks],
+template <class P, int C, int QB = 4>
+__device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[QB][P::kBlocks],
                                           const TileArgs& a, int r0, int r1, bool act,
                                           TopC<C>& top, float* tb, int lane) {
     const int g = lane >> 4;
     const int c16 = lane & 15;
-    float wq[4];
-    refresh_bounds<C>(wq, top, act, c16);
+    float wq[QB];
+    refresh_bounds<C, QB>(wq, top, act, c16);
     typename P::XFrag xa[2][P::kBlocks], xb[2][P::kBlocks];
     f4 na[2], nb[2];
     load_xfrags<P>(xa, a, r0, c16, g);
@@ -171,7 +171,7 @@ __device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[4][P::kB
         load_xfrags<P>(xb, a, nbase, c16, g);
         load_norms(nb, a.xn, nbase, r1, g);
         __builtin_amdgcn_sched_barrier(0);
-        scan_block<P, C>(qf, xa, na, base, r1, act, top, wq, tb, lane);
+        scan_block<P, C, QB>(qf, xa, na, base, r1, act, top, wq, tb, lane);
         base = next;
         if (base >= r1) break;
         next = base + kRowsMfma;
@@ -179,7 +179,7 @@ __device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[4][P::kB
         load_xfrags<P>(xa, a, nbase, c16, g);
         load_norms(na, a.xn, nbase, r1, g);
         __builtin_amdgcn_sched_barrier(0);
-        scan_block<P, C>(qf, xb, nb, base, r1, act, top, wq, tb, lane);
+        scan_block<P, C, QB>(qf, xb, nb, base, r1, act, top, wq, tb, lane);
         base = next;
         if (base >= r1) break;
     }
@@ -213,7 +213,7 @@ __device__ __forceinline__ void tile_bf_body(const TileArgs& a, float* tbuf_wave
         const int slot = slot0 + 16 * qb + c16;
         qrow[qb] = slot < m ? slot : m - 1;
     }
-    load_qfrags<P>(qf, a, qrow, g);
+    load_qfrags<P, 4>(qf, a, qrow, g);
     const int myslot = slot0 + lane;
     TopC<C> top;
     top.init();
@@ -226,13 +226,14 @@ __device__ __forceinline__ void tile_bf_body(const TileArgs& a, float* tbuf_wave
     }
 }
 
-// Item mode: persistent wavefronts, each taking (representative, 64-query
+// Item mode: persistent wavefronts, each taking (representative, 16 QB-query
 // chunk) items from the queue until it is empty.  Wavefronts work
 // independently (no workgroup barrier); consecutive items usually belong to
 // the same representative, so co-resident wavefronts share its list rows in
 // the caches.
-template <class P, int C>
+template <class P, int C, int QB = 4>
 __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_wave) {
+    constexpr int kQ = 16 * QB;  // queries per item
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
     const int c16 = lane & 15;
@@ -251,18 +252,18 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
             split = chunk % a.isplit;
             chunk /= a.isplit;
         }
-        const int q_begin = a.roff[r] + chunk * kWave;
+        const int q_begin = a.roff[r] + chunk * kQ;
         const int q_end = a.roff[r + 1];
-        typename P::QFrag qf[4][P::kBlocks];
-        int qrow[4];
+        typename P::QFrag qf[QB][P::kBlocks];
+        int qrow[QB];
 #pragma unroll
-        for (int qb = 0; qb < 4; ++qb) {
+        for (int qb = 0; qb < QB; ++qb) {
             const int p = q_begin + 16 * qb + c16;
             qrow[qb] = a.qlist[p < q_end ? p : q_end - 1];
         }
-        load_qfrags<P>(qf, a, qrow, g);
+        load_qfrags<P, QB>(qf, a, qrow, g);
         const int p = q_begin + lane;
-        const bool valid = p < q_end;
+        const bool valid = lane < kQ && p < q_end;
         const int q = a.qlist[valid ? p : q_end - 1];
         TopC<C> top;
         if (a.tau) top.seed(a.tau[q]); else top.init();
@@ -278,19 +279,19 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         // next ticket: issued after this item's metadata loads (memory
         // counters retire in issue order), consumed at the next iteration
         if (lane == 0) ticket = atomicAdd(a.item_queue, 1);
-        if (r0 < r1) scan_rows<P, C>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
+        if (r0 < r1) scan_rows<P, C, QB>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
         if (valid) {
             const int64_t pair = a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r]
                                          : (int64_t)q * (a.isplit > 1 ? a.isplit : 1) + split;
             top.store(a.pval + pair * C, a.pidx + pair * C);
         }
         if (a.stats && lane == 0) {
-            const int nq = q_end - q_begin < kWave ? q_end - q_begin : kWave;
+            const int nq = q_end - q_begin < kQ ? q_end - q_begin : kQ;
             const int nrow = r1 > r0 ? r1 - r0 : 0;
             atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)nq * nrow);
             atomicAdd((unsigned long long*)&a.stats[6], 1ull);
             atomicAdd((unsigned long long*)&a.stats[7],
-                      (unsigned long long)kWave * ((nrow + kRowsMfma - 1) / kRowsMfma * kRowsMfma));
+                      (unsigned long long)kQ * ((nrow + kRowsMfma - 1) / kRowsMfma * kRowsMfma));
         }
     }
 }
@@ -338,7 +339,7 @@ __device__ __forceinline__ void tile_recs_body(const TileArgs& a, float* tbuf_wa
         const int4 nr1 = *(const int4*)(a.irec + (int64_t)kItemRec * nrec + 4);
         if (lane == 0 && more) ticket = atomicAdd(a.item_queue, 1);
         typename P::QFrag qf[4][P::kBlocks];
-        load_qfrags<P>(qf, a, qrow, g);
+        load_qfrags<P, 4>(qf, a, qrow, g);
         TopC<C> top;
         if (a.tau) top.seed(a.tau[q]); else top.init();
         const int64_t pair = (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r];
@@ -373,7 +374,7 @@ __device__ __forceinline__ void tile_all_body(const TileArgs& a) {
         const int slot = slot0 + 16 * qb + c16;
         qrow[qb] = slot < a.m ? slot : a.m - 1;
     }
-    load_qfrags<P>(qf, a, qrow, g);
+    load_qfrags<P, 4>(qf, a, qrow, g);
     const int r0 = (int)((int64_t)blockIdx.y * a.rps);
     const int r1 = (int)(r0 + (int64_t)a.rps < a.n ? r0 + a.rps : a.n);
     if (r0 >= r1) return;
@@ -389,7 +390,7 @@ __device__ __forceinline__ void tile_all_body(const TileArgs& a) {
         load_xfrags<P>(xb, a, nbase, c16, g);
         load_norms(nb, a.xn, nbase, r1, g);
         f4 acc[2][4];
-        tile_step<P>(acc, qf, xa, na, base, r1, g);
+        tile_step<P, 4>(acc, qf, xa, na, base, r1, g);
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
             const int row = base + 16 * rb + 4 * g;

@@ -57,9 +57,10 @@ def test_bf_pinned_shape(rbc, orc, shape, n, m, d, k):
     assert_knn_parity(idx, dist, Q, X, k, "l2", orc)
 
 
-@pytest.mark.parametrize("shape,blocks", [(16, 1024), (32, 1024), (32, 300), (16, 7)])
+@pytest.mark.parametrize("shape,blocks,splits", [(16, 1024, 0), (32, 1024, 0), (32, 300, 1),
+                                                 (16, 7, 3), (16, 1024, 8)])
 @pytest.mark.parametrize("k", [1, 10])
-def test_search_pinned_shape(rbc, orc, shape, blocks, k):
+def test_search_pinned_shape(rbc, orc, shape, blocks, splits, k):
     """Exact RBC search (two passes) on the small workload under each pinned
     stage-2 configuration, including a persistent grid smaller than the
     device and one that is not a power of two."""
@@ -68,7 +69,7 @@ def test_search_pinned_shape(rbc, orc, shape, blocks, k):
     X, Q = datagen.database("iid16"), datagen.queries("iid16")
     reps = datagen.representatives("iid16")
     ix = rbc.rbc_build(_dev(X), len(reps), rep_idx=reps)
-    rbc.autotune_set("search", X.shape[1], _shortlist(k), shape, blocks)
+    rbc.autotune_set("search", X.shape[1], _shortlist(k), shape, blocks, splits)
     try:
         idx, dist = rbc.rbc_search(ix, _dev(Q), k)
         torch.cuda.synchronize()
@@ -113,7 +114,8 @@ def test_autotune_search_and_bf(rbc, orc):
     try:
         r = rbc.autotune_search(ix, Qd, 1)
         assert r["shape"] in (16, 32) and r["blocks"] in (512, 1024, 2048)
-        assert r["candidates"] == 6 and r["ms"] > 0 and r["ms_before"] >= r["ms"]
+        assert r["splits"] in (0, 2, 4)
+        assert r["candidates"] == 18 and r["ms"] > 0 and r["ms_before"] >= r["ms"]
         idx, dist = rbc.rbc_search(ix, Qd, 1)
         b = rbc.autotune_bf(Qd, Xd, 1)
         assert b["shape"] in (16, 32) and b["candidates"] == 2
