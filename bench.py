@@ -217,7 +217,7 @@ def main():
     if metric == "l2":
         kname = ("tile_l2_mfma32_items" if tuning.get("rbc_search", {}).get("shape") == 32
                  else "tile_l2_mfma_items")
-    roofline["traffic"] = (profiled_traffic("void rbc::%s<4, 4>" % kname)
+    roofline["traffic"] = (profiled_traffic("void rbc::%s<4, 4>(rbc::TileArgs)" % kname)
                            if (metric, k) == ("l2", 1) else None)
     roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)"
     roofline["kernel"] = kname + " (RBC stage 2)"
@@ -228,6 +228,9 @@ def main():
     bf_avg = bf_tile_ms / max(bf_tile_n, 1)
     bf_roof = roof(per_pair * m * n, bf_avg)
     bf_roof["avg_ms"] = round(bf_avg, 4)
+    bf_roof["kernel"] = "tile_l2_mfma (brute force)" if metric == "l2" else "tile_valu (brute force)"
+    bf_roof["traffic"] = (profiled_traffic("void rbc::tile_l2_mfma<4, 4>(rbc::TileArgs)")
+                          if (metric, k) == ("l2", 1) else None)
 
     extra = {}
     if args.extra:
