@@ -301,11 +301,13 @@ int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);
  * already holds one query per lane -- and the grouped stage-2 search of the
  * exact RBC (Sec. 5.2) is one persistent launch whose workgroup count is
  * free.  Which is fastest depends on d, the shortlist length and the list
- * sizes.  Untuned, the library uses the 16x16 shape and 1024 workgroups.
+ * sizes.  Untuned, the library uses the 16x16 shape, 64-query stage-2 items
+ * and 1024 workgroups.
  *
  * rbc_autotune_search runs the given rbc_search once untimed and three times
- * timed (HIP events on hip_stream) under each candidate (2 shapes x 512 /
- * 1024 / 2048 workgroups x pass-1 splits by the size rule, 2 or 4),
+ * timed (HIP events on hip_stream) under each candidate (16x16 with 64- or
+ * 32-query stage-2 items, or 32x32; x 512 / 1024 / 2048 workgroups x pass-1
+ * splits by the size rule or 2),
  * rbc_autotune_bf likewise for bf_search (2 shapes); the fastest is kept,
  * process-wide, for every later call with the
  * same launch kind, 16-feature slab count (ceil(d / 16)) and shortlist
@@ -320,6 +322,7 @@ typedef struct rbc_tune_result {
     int32_t shape;       /* 16 or 32 */
     int32_t blocks;      /* persistent workgroups (stage-2 launch; bf: unused) */
     int32_t splits;      /* row ranges per nearest list in pass 1 (0: size rule; bf: unused) */
+    int32_t item_queries; /* queries per stage-2 item, 64 or 32 (bf: 64, unused) */
     float ms;            /* best time of the chosen candidate, whole call */
     float ms_before;     /* the same for the configuration used before tuning */
     int32_t candidates;  /* configurations timed */
@@ -337,9 +340,11 @@ int rbc_autotune_bf(const float* Q, int64_t m, int64_t ldq, const float* X, int6
  * the exact-index fallback tile), 1 = rbc_search (stage 2 and pass 1); d and
  * shortlist (4, 8, 16, 32 or 64) select the entry as above; shape 16 or 32;
  * blocks the stage-2 workgroup count; splits 0 .. 8 the pass-1 row ranges per
- * nearest list (0: the size rule).  RBC_EINVAL on values out of range. */
+ * nearest list (0: the size rule); item_queries 64, or 32 with shape 16 (the
+ * queries of one stage-2 item of the two-pass search).  RBC_EINVAL on values
+ * out of range. */
 int rbc_autotune_set(int32_t kind, int32_t d, int32_t shortlist, int32_t shape, int32_t blocks,
-                     int32_t splits);
+                     int32_t splits, int32_t item_queries);
 /* Forget every tuned choice (later calls use the fixed rule). */
 void rbc_autotune_clear(void);
 

@@ -47,7 +47,8 @@ class BuildParams(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("shape", _I32), ("blocks", _I32), ("splits", _I32), ("ms", ctypes.c_float),
+    _fields_ = [("shape", _I32), ("blocks", _I32), ("splits", _I32), ("item_queries", _I32),
+                ("ms", ctypes.c_float),
                 ("ms_before", ctypes.c_float), ("candidates", _I32)]
 
 
@@ -90,7 +91,7 @@ def lib():
                                           ctypes.POINTER(TuneResult)]
         L.rbc_autotune_bf.argtypes = [_P, _I64, _I64, _P, _I64, _I64, _I32, _I32, _I32, _P, _P,
                                       _P, _P, _SZ, _P, ctypes.POINTER(TuneResult)]
-        L.rbc_autotune_set.argtypes = [_I32, _I32, _I32, _I32, _I32, _I32]
+        L.rbc_autotune_set.argtypes = [_I32, _I32, _I32, _I32, _I32, _I32, _I32]
         L.rbc_autotune_clear.argtypes = []
         L.rbc_autotune_clear.restype = None
         L.rbc_timer_enable.argtypes = [ctypes.c_int]
@@ -336,7 +337,8 @@ def rbc_range_search(index, Q, radius, workspace=None):
 
 
 def _tune_dict(r):
-    return {"shape": r.shape, "blocks": r.blocks, "splits": r.splits, "ms": r.ms,
+    return {"shape": r.shape, "blocks": r.blocks, "splits": r.splits,
+            "item_queries": r.item_queries, "ms": r.ms,
             "ms_before": r.ms_before,
             "candidates": r.candidates}
 
@@ -381,10 +383,10 @@ def autotune_bf(Q, X, k, metric="l2", **kw):
     return _tune_dict(r)
 
 
-def autotune_set(kind, d, shortlist, shape, blocks=1024, splits=0):
+def autotune_set(kind, d, shortlist, shape, blocks=1024, splits=0, item_queries=64):
     """Pin the tile choice of kind "bf" or "search" for (d, shortlist length)."""
     _check(lib().rbc_autotune_set({"bf": 0, "search": 1}[kind], d, shortlist, shape, blocks,
-                                  splits))
+                                  splits, item_queries))
 
 
 def autotune_clear():

@@ -752,6 +752,34 @@ hipError_t launch_tau_home(const float* hval, int32_t c, int32_t nsplit, int32_t
 // With rec non-null the item's record is written as well (representative,
 // first and end query position, row run, item) and its cost class (queries x
 // 32-row blocks, see item_cost) is counted in hist.
+// First position j in [L, R) of the ascending own[] with own[j] >= v
+// (after_equal: own[j] > v), or R: a 64-way search, each lane probing one
+// pivot per round, so a list of up to 262,144 rows needs three rounds of
+// loads instead of eighteen dependent ones.
+__device__ __forceinline__ int wave_bound(const float* own, int L, int R, double v,
+                                          bool after_equal, int lane) {
+    while (R - L > 64) {
+        const int64_t span = R - L;
+        const int s = L + (int)(span * lane / 64);
+        const double x = (double)own[s];
+        const bool below = after_equal ? x <= v : x < v;
+        const int c = __popcll(__ballot(below));  // pivots before the answer (a prefix)
+        if (c == 0) return L;                     // own[L] already at or past v
+        // answer in (pivot c - 1, pivot c]; pivot 64 is R
+        const int nl = L + (int)(span * (c - 1) / 64) + 1;
+        const int nr = c < 64 ? L + (int)(span * c / 64) : R;
+        L = nl;
+        R = nr;
+    }
+    const int s = L + lane;
+    bool below = false;
+    if (s < R) {
+        const double x = (double)own[s];
+        below = after_equal ? x <= v : x < v;
+    }
+    return L + __popcll(__ballot(below));
+}
+
 __device__ __forceinline__ int item_cost(int nq, int lo, int hi) {
     const int c = (nq * ((hi - lo + 31) >> 5)) >> 3;
     return c < kCostBuckets - 1 ? c : kCostBuckets - 1;
@@ -790,18 +818,8 @@ __global__ __launch_bounds__(256) void item_rows_kernel(
                 vhi = fmax(vhi, __shfl_xor(vhi, off));
             }
             // first row with own >= vlo, first row with own > vhi
-            int l = b, h = e;
-            while (l < h) {
-                const int mid = (l + h) >> 1;
-                if ((double)own[mid] < vlo) l = mid + 1; else h = mid;
-            }
-            lo = l;
-            h = e;
-            while (l < h) {
-                const int mid = (l + h) >> 1;
-                if ((double)own[mid] <= vhi) l = mid + 1; else h = mid;
-            }
-            hi = l;
+            lo = wave_bound(own, b, e, vlo, false, lane);
+            hi = wave_bound(own, lo, e, vhi, true, lane);
         }
         if (lane == 0) {
             irows[2 * (int64_t)item] = lo;

@@ -65,6 +65,19 @@ __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_ite
         tile_items_body<Fp32Policy<KS>, C>(a, tbuf[threadIdx.x >> 6]);
 }
 
+// Stage 2 on 32-query items (two query blocks per wavefront): narrower row
+// runs per item and about 170 VGPRs, so three wavefronts per SIMD.
+template <int KS, int C>
+struct Mfma32qOcc {
+    static constexpr int value = (16 * KS + 2 * C + 96 <= 168) ? 3 : (MfmaOcc<KS, C>::value);
+};
+
+template <int KS, int C>
+__global__ __launch_bounds__(256, (Mfma32qOcc<KS, C>::value)) void tile_l2_mfma_items32q(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
+    tile_recs_body<Fp32Policy<KS>, C, 2>(a, tbuf[threadIdx.x >> 6]);
+}
+
 // Pass 1 of the two-pass search: the item body over the nearest lists, with
 // 16-query items (one query block per wavefront): a nearest list holds few
 // queries (about m / n_r), so wider items would mostly score empty slots.
@@ -101,6 +114,8 @@ static hipError_t launch_c(int mode, dim3 grid, const TileArgs& a, hipStream_t s
         hipLaunchKernelGGL((tile_l2_mfma32<KS, C>), grid, dim3(256), 0, st, a);
     else if (a.shape == kShape32 && mode == kTileItems && a.irec)
         hipLaunchKernelGGL((tile_l2_mfma32_items<KS, C>), grid, dim3(256), 0, st, a);
+    else if (a.qb == 2 && mode == kTileItems && a.irec)
+        hipLaunchKernelGGL((tile_l2_mfma_items32q<KS, C>), grid, dim3(256), 0, st, a);
     else if (mode == kTileItems)
         hipLaunchKernelGGL((tile_l2_mfma_items<KS, C>), grid, dim3(256), 0, st, a);
     else if (mode == kTileHome)

@@ -85,6 +85,8 @@ struct TileArgs {
     int64_t ldo;           // kTileAll: row stride of the value matrix
     int64_t* stats;        // optional device counters
     int32_t shape;         // fp32 matrix tile: kShape16 or kShape32
+    int32_t qb;            // stage-2 items with records, 16x16 shape: 16-query blocks per
+                           // item (4, or 2 for 32-query items; 0 means 4)
     // BF mode with a device-side query count (non-null m_dev): the first
     // *m_dev rows of Q are searched by a 1-D grid of dev_blocks workgroups
     // whose (query block, split) layout is derived from the count (dev_split)

@@ -124,6 +124,7 @@ struct TileChoice {
     int shape = kShape16;
     int blocks = kItemBlocks;
     int splits = 0;  // row ranges per nearest list in pass 1 (0: the size rule)
+    int qb = 4;      // stage 2, 16x16 shape: 16-query blocks per item (4 or 2)
 };
 TileChoice tile_choice(int kind, int ks, int c);
 

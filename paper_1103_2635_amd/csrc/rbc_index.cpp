@@ -644,6 +644,15 @@ int search_oneshot(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t
 // Pass 1 of the two-pass search splits each nearest list into this many row
 // ranges (one work item each, about 128 rows or more), so that the few
 // queries of a list are served by several wavefronts.
+// 16-query blocks per stage-2 item: 2 only for the two-pass search on the
+// 16x16 fp32 tile when the tuned choice says so (the item records exist on
+// that path alone), else 4 (64-query items).
+int stage2_qb(const BfPlan& p) {
+    if (p.path != kPathMfma || !p.two_pass) return 4;
+    const TileChoice tc = tile_choice(kTuneItems, p.ks, p.c);
+    return (tc.shape == kShape16 && tc.qb == 2) ? 2 : 4;
+}
+
 int home_splits(const rbc_index* ix, const BfPlan& p) {
     const TileChoice tc = tile_choice(kTuneItems, p.ks, p.c);
     if (tc.splits > 0) return std::min(tc.splits, kMaxHomeSplit);
@@ -679,7 +688,9 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
     w->roff = cv.take<int32_t>(nr + 1);
     w->ioff = cv.take<int32_t>(nr + 1);
     w->qlist = cv.take<int32_t>(m * nr);
-    w->irep = cv.take<int32_t>(m * nr / kWave + nr + 1);
+    // stage-2 items hold 64 or 32 queries (matrix path), 256 (vector path)
+    const int64_t max_items = m * nr / 32 + nr + 1;
+    w->irep = cv.take<int32_t>(max_items);
     if (p.two_pass) {
         w->home = cv.take<int32_t>(m);
         w->qa = cv.take<int32_t>(m);
@@ -691,10 +702,10 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         w->hval = cv.take<float>(m * kMaxHomeSplit * p.c);
         w->hidx = cv.take<int32_t>(m * kMaxHomeSplit * p.c);
         w->taud = cv.take<float>(m);
-        w->irows = cv.take<int32_t>(2 * (m * nr / kWave + nr + 1));
+        w->irows = cv.take<int32_t>(2 * max_items);
         if (p.path == kPathMfma) {
-            w->rec = cv.take<int32_t>(kItemRec * (m * nr / kWave + nr + 1));
-            w->srec = cv.take<int32_t>(kItemRec * (m * nr / kWave + nr + 1));
+            w->rec = cv.take<int32_t>(kItemRec * max_items);
+            w->srec = cv.take<int32_t>(kItemRec * max_items);
             w->chist = cv.take<int32_t>(kCostBuckets);
         }
     }
@@ -888,7 +899,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                                        hipMemcpyDeviceToDevice, st), "copy counts")))
             return rc;
         if ((rc = check(launch_scan_total(w.qoff, m, st), "pair offsets"))) return rc;
-        const int32_t isize = p.path == kPathValu ? kTileQ : kWave;
+        const int32_t isize = p.path == kPathValu ? kTileQ : 16 * stage2_qb(p);
         if ((rc = check(launch_worklist(w.keep_rq, (int32_t)m, nr, isize, w.roff, w.ioff, w.qlist,
                                         st), "work list")))
             return rc;
@@ -959,6 +970,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     a.irec = w.srec;
     const TileChoice tc = tile_choice(kTuneItems, p.ks, p.c);
     a.shape = tc.shape;
+    a.qb = stage2_qb(p);
     {
         KernelTimer kt("tile_items", st);
         const dim3 grid(tc.blocks);

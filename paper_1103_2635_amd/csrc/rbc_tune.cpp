@@ -1,6 +1,7 @@
 // rbc_tune.cpp -- the tile autotuner: which fp32 matrix-core tile shape
 // (16x16x4 with an LDS transpose, or 32x32x2 without) and, for the exact
-// search, how many workgroups the persistent stage-2 launch has and into how
+// search, how many queries a stage-2 item holds (64, or 32 on the 16x16
+// shape), how many workgroups the persistent stage-2 launch has and into how
 // many row ranges pass 1 splits each nearest list, per (launch kind,
 // 16-feature slab count, shortlist length).
 //
@@ -90,7 +91,8 @@ int pick(int kind, int ks, int c, const std::vector<Candidate>& res, rbc_tune_re
     float def_ms = -1.f;
     for (const Candidate& r : res) {
         if (!best || r.ms < best->ms) best = &r;
-        if (r.t.shape == def.shape && r.t.blocks == def.blocks && r.t.splits == def.splits)
+        if (r.t.shape == def.shape && r.t.blocks == def.blocks && r.t.splits == def.splits &&
+            r.t.qb == def.qb)
             def_ms = r.ms;
     }
     if (!best) return set_err(RBC_EINVAL, "no candidate configuration");
@@ -102,6 +104,7 @@ int pick(int kind, int ks, int c, const std::vector<Candidate>& res, rbc_tune_re
         out->shape = best->t.shape == kShape32 ? 32 : 16;
         out->blocks = best->t.blocks;
         out->splits = best->t.splits;
+        out->item_queries = 16 * best->t.qb;
         out->ms = best->ms;
         out->ms_before = def_ms;
         out->candidates = (int32_t)res.size();
@@ -143,12 +146,14 @@ int rbc_autotune_search(const rbc_index* ix, const float* Q, int64_t m, int64_t 
         if (rc) return rc;
         if (kind < 0) return set_err(RBC_EUNSUPPORTED,
                                      "this search runs no tunable matrix-core launch");
+        // tile variants: 16x16 with 64- or 32-query items, 32x32 with 64
         std::vector<TileChoice> cands;
-        for (int sh : {kShape16, kShape32})
+        for (int v = 0; v < 3; ++v)
             for (int blocks : {kItemBlocks / 2, kItemBlocks, 2 * kItemBlocks})
-                for (int splits : {0, 2, 4}) {
+                for (int splits : {0, 2}) {
                     TileChoice t;
-                    t.shape = sh;
+                    t.shape = v == 2 ? kShape32 : kShape16;
+                    t.qb = v == 1 ? 2 : 4;
                     t.blocks = blocks;
                     t.splits = splits;
                     cands.push_back(t);
@@ -191,7 +196,7 @@ int rbc_autotune_bf(const float* Q, int64_t m, int64_t ldq, const float* X, int6
 }
 
 int rbc_autotune_set(int32_t kind, int32_t d, int32_t shortlist, int32_t shape,
-                     int32_t blocks, int32_t splits) {
+                     int32_t blocks, int32_t splits, int32_t item_queries) {
     if (kind != 0 && kind != 1) return set_err(RBC_EINVAL, "kind must be 0 (bf) or 1 (search)");
     if (d < 1 || d > 16 * kMaxKS) return set_err(RBC_EINVAL, "d must be in 1 .. %d", 16 * kMaxKS);
     if (shortlist != 4 && shortlist != 8 && shortlist != 16 && shortlist != 32 && shortlist != 64)
@@ -200,10 +205,13 @@ int rbc_autotune_set(int32_t kind, int32_t d, int32_t shortlist, int32_t shape,
     if (blocks < 1 || blocks > 65536) return set_err(RBC_EINVAL, "blocks must be in 1 .. 65536");
     if (splits < 0 || splits > kMaxHomeSplit)
         return set_err(RBC_EINVAL, "splits must be in 0 .. %d", kMaxHomeSplit);
+    if (item_queries != 64 && !(item_queries == 32 && shape == 16))
+        return set_err(RBC_EINVAL, "item_queries must be 64, or 32 with shape 16");
     TileChoice t;
     t.shape = shape == 32 ? kShape32 : kShape16;
     t.blocks = blocks;
     t.splits = splits;
+    t.qb = item_queries / 16;
     std::lock_guard<std::mutex> lk(g_mu);
     g_table[std::make_tuple(kind == 0 ? kTuneBF : kTuneItems, (d + 15) / 16, shortlist)] = t;
     return RBC_OK;

@@ -303,8 +303,9 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
 // starts with the loads of its query ids; the next record and the next ticket
 // are loaded while the current item is scanned, and the output slot of each
 // query is looked up before the scan.
-template <class P, int C>
+template <class P, int C, int QB = 4>
 __device__ __forceinline__ void tile_recs_body(const TileArgs& a, float* tbuf_wave) {
+    constexpr int kQ = 16 * QB;  // queries per item
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
     const int c16 = lane & 15;
@@ -322,14 +323,14 @@ __device__ __forceinline__ void tile_recs_body(const TileArgs& a, float* tbuf_wa
         const int q_end = __builtin_amdgcn_readfirstlane(rc0.z);
         const int r0 = __builtin_amdgcn_readfirstlane(rc0.w);
         const int r1 = __builtin_amdgcn_readfirstlane(rc1.x);
-        int qrow[4];
+        int qrow[QB];
 #pragma unroll
-        for (int qb = 0; qb < 4; ++qb) {
+        for (int qb = 0; qb < QB; ++qb) {
             const int p = q_begin + 16 * qb + c16;
             qrow[qb] = a.qlist[p < q_end ? p : q_end - 1];
         }
         const int p = q_begin + lane;
-        const bool valid = p < q_end;
+        const bool valid = lane < kQ && p < q_end;
         const int q = a.qlist[valid ? p : q_end - 1];
         // the ticket taken during the previous item names the next record
         const int nxt = __builtin_amdgcn_readfirstlane(__shfl(ticket, 0));
@@ -338,20 +339,20 @@ __device__ __forceinline__ void tile_recs_body(const TileArgs& a, float* tbuf_wa
         const int4 nr0 = *(const int4*)(a.irec + (int64_t)kItemRec * nrec);
         const int4 nr1 = *(const int4*)(a.irec + (int64_t)kItemRec * nrec + 4);
         if (lane == 0 && more) ticket = atomicAdd(a.item_queue, 1);
-        typename P::QFrag qf[4][P::kBlocks];
-        load_qfrags<P, 4>(qf, a, qrow, g);
+        typename P::QFrag qf[QB][P::kBlocks];
+        load_qfrags<P, QB>(qf, a, qrow, g);
         TopC<C> top;
         if (a.tau) top.seed(a.tau[q]); else top.init();
         const int64_t pair = (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r];
-        if (r0 < r1) scan_rows<P, C>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
+        if (r0 < r1) scan_rows<P, C, QB>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
         if (valid) top.store(a.pval + pair * C, a.pidx + pair * C);
         if (a.stats && lane == 0) {
-            const int nq = q_end - q_begin < kWave ? q_end - q_begin : kWave;
+            const int nq = q_end - q_begin < kQ ? q_end - q_begin : kQ;
             const int nrow = r1 > r0 ? r1 - r0 : 0;
             atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)nq * nrow);
             atomicAdd((unsigned long long*)&a.stats[6], 1ull);
             atomicAdd((unsigned long long*)&a.stats[7],
-                      (unsigned long long)kWave * ((nrow + kRowsMfma - 1) / kRowsMfma * kRowsMfma));
+                      (unsigned long long)kQ * ((nrow + kRowsMfma - 1) / kRowsMfma * kRowsMfma));
         }
         if (!more) break;
         rc0 = nr0;

@@ -64,11 +64,14 @@ def test_bf_workspace_size_and_validation(lib):
 
 
 def test_autotune_set_validation(lib):
-    assert lib.rbc_autotune_set(1, 64, 4, 32, 512, 0) == 0
-    assert lib.rbc_autotune_set(0, 128, 16, 16, 1024, 4) == 0
-    for args in [(2, 64, 4, 16, 512, 0), (1, 0, 4, 16, 512, 0), (1, 129, 4, 16, 512, 0),
-                 (1, 64, 5, 16, 512, 0), (1, 64, 4, 24, 512, 0), (1, 64, 4, 16, 0, 0),
-                 (1, 64, 4, 16, 512, 9), (1, 64, 4, 16, 512, -1)]:
+    assert lib.rbc_autotune_set(1, 64, 4, 32, 512, 0, 64) == 0
+    assert lib.rbc_autotune_set(0, 128, 16, 16, 1024, 4, 64) == 0
+    assert lib.rbc_autotune_set(1, 64, 4, 16, 1024, 2, 32) == 0
+    for args in [(2, 64, 4, 16, 512, 0, 64), (1, 0, 4, 16, 512, 0, 64),
+                 (1, 129, 4, 16, 512, 0, 64), (1, 64, 5, 16, 512, 0, 64),
+                 (1, 64, 4, 24, 512, 0, 64), (1, 64, 4, 16, 0, 0, 64),
+                 (1, 64, 4, 16, 512, 9, 64), (1, 64, 4, 16, 512, -1, 64),
+                 (1, 64, 4, 32, 512, 0, 32), (1, 64, 4, 16, 512, 0, 48)]:
         assert lib.rbc_autotune_set(*args) == EINVAL, args
     lib.rbc_autotune_clear()
 

@@ -57,10 +57,12 @@ def test_bf_pinned_shape(rbc, orc, shape, n, m, d, k):
     assert_knn_parity(idx, dist, Q, X, k, "l2", orc)
 
 
-@pytest.mark.parametrize("shape,blocks,splits", [(16, 1024, 0), (32, 1024, 0), (32, 300, 1),
-                                                 (16, 7, 3), (16, 1024, 8)])
+@pytest.mark.parametrize("shape,blocks,splits,iq", [(16, 1024, 0, 64), (32, 1024, 0, 64),
+                                                    (32, 300, 1, 64), (16, 7, 3, 64),
+                                                    (16, 1024, 8, 64), (16, 1024, 2, 32),
+                                                    (16, 200, 0, 32)])
 @pytest.mark.parametrize("k", [1, 10])
-def test_search_pinned_shape(rbc, orc, shape, blocks, splits, k):
+def test_search_pinned_shape(rbc, orc, shape, blocks, splits, iq, k):
     """Exact RBC search (two passes) on the small workload under each pinned
     stage-2 configuration, including a persistent grid smaller than the
     device and one that is not a power of two."""
@@ -69,7 +71,7 @@ def test_search_pinned_shape(rbc, orc, shape, blocks, splits, k):
     X, Q = datagen.database("iid16"), datagen.queries("iid16")
     reps = datagen.representatives("iid16")
     ix = rbc.rbc_build(_dev(X), len(reps), rep_idx=reps)
-    rbc.autotune_set("search", X.shape[1], _shortlist(k), shape, blocks, splits)
+    rbc.autotune_set("search", X.shape[1], _shortlist(k), shape, blocks, splits, iq)
     try:
         idx, dist = rbc.rbc_search(ix, _dev(Q), k)
         torch.cuda.synchronize()
@@ -79,10 +81,11 @@ def test_search_pinned_shape(rbc, orc, shape, blocks, splits, k):
     assert_knn_parity(idx, dist, Q, X, k, "l2", orc)
 
 
-def test_search_pinned_shape_headline_sample(rbc, orc):
-    """The 10^6 x 64 subspace workload with the 32x32 shape pinned for the
-    stage-2 launch: a sample of queries checked against the oracle's
-    brute force."""
+@pytest.mark.parametrize("shape,iq", [(32, 64), (16, 32)])
+def test_search_pinned_shape_headline_sample(rbc, orc, shape, iq):
+    """The 10^6 x 64 subspace workload with the 32x32 shape or 32-query items
+    pinned for the stage-2 launch: a sample of queries checked against the
+    oracle's brute force."""
     import torch
 
     name = "sub8"
@@ -91,7 +94,7 @@ def test_search_pinned_shape_headline_sample(rbc, orc):
     Q = datagen.queries(name)[:2000]
     reps = datagen.representatives(name)
     ix = rbc.rbc_build(_dev(X), w.n_r, rep_idx=reps)
-    rbc.autotune_set("search", X.shape[1], 4, 32, 1024)
+    rbc.autotune_set("search", X.shape[1], 4, shape, 1024, 0, iq)
     try:
         idx, dist = rbc.rbc_search(ix, _dev(Q), 1)
         torch.cuda.synchronize()
@@ -114,7 +117,7 @@ def test_autotune_search_and_bf(rbc, orc):
     try:
         r = rbc.autotune_search(ix, Qd, 1)
         assert r["shape"] in (16, 32) and r["blocks"] in (512, 1024, 2048)
-        assert r["splits"] in (0, 2, 4)
+        assert r["splits"] in (0, 2) and r["item_queries"] in (32, 64)
         assert r["candidates"] == 18 and r["ms"] > 0 and r["ms_before"] >= r["ms"]
         idx, dist = rbc.rbc_search(ix, Qd, 1)
         b = rbc.autotune_bf(Qd, Xd, 1)
