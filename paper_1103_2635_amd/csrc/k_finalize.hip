@@ -37,17 +37,8 @@ __device__ __forceinline__ int wave_argmin(float v, int32_t id, float& bv, int32
 }
 
 template <int C>
-__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+__device__ __forceinline__ void finalize_slot(const FinArgs& a, int slot, int nsplit, int stride) {
     const int lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
-    int mact = a.m, nsplit = a.nsplit, stride = a.m;
-    if (a.m_dev) {
-        mact = *a.m_dev;
-        const DevSplit ds = dev_split(mact, a.dev_blocks, a.n);
-        nsplit = ds.S;
-        stride = ds.M;
-    }
-    if (slot >= mact) return;  // uniform per wavefront
     const int qrow = slot;                               // row of Q (and of qn, qerr)
     const int orow = a.qmap ? a.qmap[slot] : slot;       // output row, reported query
 
@@ -215,6 +206,22 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     }
 }
 
+// One wavefront per query.  With a device-side query count (the float32
+// cascade of low-precision searches) the grid is bounded and strides over
+// the queries, so a launch sized for every query costs nothing when few fail.
+template <int C>
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+    int mact = a.m, nsplit = a.nsplit, stride = a.m;
+    if (a.m_dev) {
+        mact = *a.m_dev;
+        const DevSplit ds = dev_split(mact, a.dev_blocks, a.n);
+        nsplit = ds.S;
+        stride = ds.M;
+    }
+    for (int slot = blockIdx.x * 4 + (threadIdx.x >> 6); slot < mact; slot += gridDim.x * 4)
+        finalize_slot<C>(a, slot, nsplit, stride);  // uniform per wavefront
+}
+
 // The same steps for the common case of one list per query (a single
 // database split, no pair lists, c <= 16), with 16 lanes per query and four
 // queries per wavefront: 16 / c lanes re-score each candidate.  Shuffles stay
@@ -360,7 +367,8 @@ hipError_t launch_finalize(int c, const FinArgs& a, hipStream_t st) {
         }
         return hipGetLastError();
     }
-    const dim3 grid((a.m + 3) / 4);
+    const int64_t waves = a.m_dev && a.m > 8192 ? 8192 : a.m;
+    const dim3 grid((unsigned)((waves + 3) / 4));
     switch (c) {
         case 4: hipLaunchKernelGGL((finalize_kernel<4>), grid, dim3(256), 0, st, a); break;
         case 8: hipLaunchKernelGGL((finalize_kernel<8>), grid, dim3(256), 0, st, a); break;

@@ -146,16 +146,9 @@ hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d
 // of Qc (ldc floats, zero beyond d) is query list[i], qn[i] its squared norm
 // (fp32, a wavefront sum), qmap[i] = list[i]; *count_out = *count.  One
 // wavefront per row.
-__global__ __launch_bounds__(256) void cascade_gather_kernel(const float* Q, int64_t ldq,
-                                                             int32_t d, const int32_t* list,
-                                                             const int32_t* count, float* Qc,
-                                                             int64_t ldc, float* qn,
-                                                             int32_t* qmap, int32_t* count_out) {
-    const int cnt = *count;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = cnt;
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= cnt) return;
+__device__ __forceinline__ void gather_one(const float* Q, int64_t ldq, int32_t d,
+                                           const int32_t* list, float* Qc, int64_t ldc, float* qn,
+                                           int32_t* qmap, int64_t i, int lane) {
     const int32_t q = list[i];
     const float* src = Q + (int64_t)q * ldq;
     float* dst = Qc + i * ldc;
@@ -173,12 +166,26 @@ __global__ __launch_bounds__(256) void cascade_gather_kernel(const float* Q, int
     }
 }
 
+__global__ __launch_bounds__(256) void cascade_gather_kernel(const float* Q, int64_t ldq,
+                                                             int32_t d, const int32_t* list,
+                                                             const int32_t* count, float* Qc,
+                                                             int64_t ldc, float* qn,
+                                                             int32_t* qmap, int32_t* count_out) {
+    const int cnt = *count;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = cnt;
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < cnt;
+         i += (int64_t)gridDim.x * 4)
+        gather_one(Q, ldq, d, list, Qc, ldc, qn, qmap, i, lane);
+}
+
 hipError_t launch_cascade_gather(const float* Q, int64_t ldq, int32_t d, int64_t m,
                                  const int32_t* list, const int32_t* count, float* Qc,
                                  int64_t ldc, float* qn, int32_t* qmap, int32_t* count_out,
                                  hipStream_t st) {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(cascade_gather_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, Q,
+    const int64_t waves = m > 8192 ? 8192 : m;  // grid-stride over the device-side count
+    hipLaunchKernelGGL(cascade_gather_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, Q,
                        ldq, d, list, count, Qc, ldc, qn, qmap, count_out);
     return hipGetLastError();
 }
