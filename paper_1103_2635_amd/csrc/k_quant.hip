@@ -8,6 +8,8 @@
 // largest row norm and the largest error go to stat words through integer
 // atomic maxima on non-negative float bits.
 //   stat[0] = max ||x~||, stat[1] = max ||x - x~||.
+#include <cmath>
+
 #include "rbc_device.h"
 #include "rbc_kernels.h"
 
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
                                                        int32_t d, float mult, void* out,
                                                        int64_t ldo, int32_t dpad, float* norm2,
                                                        float* err, uint8_t* scale_out,
-                                                       uint32_t* stat) {
+                                                       uint32_t* stat, bool vec4, float inv) {
     __shared__ float wmax[4][2];
     const int sub = threadIdx.x & 15;
     float nmax = 0.f, emax = 0.f;
@@ -100,6 +102,27 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
             if (sub == 0) scale_out[r] = (uint8_t)(e + 127);
         }
         float s2 = 0.f, e2 = 0.f;
+        if (FMT == 0 && vec4) {
+            // float4 runs 4 sub + 64 j, four bf16 stored together; mult is
+            // a power of two, so dividing by it is the exact product inv
+            for (int f = 4 * sub; f < dpad; f += 64) {
+                f4 v = {0.f, 0.f, 0.f, 0.f};
+                if (f < d) v = *(const f4*)(p + f);
+                uint16_t b[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    b[e] = f32_to_bf16_rne(mult * v[e]);
+                    const float deq = bf16_to_f32(b[e]) * inv;
+                    s2 = __builtin_fmaf(deq, deq, s2);
+                    const float t = v[e] - deq;
+                    e2 = __builtin_fmaf(t, t, e2);
+                }
+                uint2 w;
+                w.x = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
+                w.y = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
+                *(uint2*)((uint16_t*)out + r * ldo + f) = w;
+            }
+        } else
         for (int f = sub; f < dpad; f += 16) {
             const float v = f < d ? p[f] : 0.f;
             float deq;  // the quantised value of v (without mult)
@@ -157,13 +180,19 @@ hipError_t launch_quantize(int fmt, const float* A, int64_t rows, int64_t lda, i
                            float* err, uint8_t* scale_out, uint32_t* stat, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     int64_t blocks = (rows * 16 + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 4096) blocks = 4096;
+    // bf16 float4 path: aligned runs and a power-of-two multiplier
+    int mexp = 0;
+    const bool pow2 = mult != 0.f && std::fabs(std::frexp(mult, &mexp)) == 0.5f;
+    const bool vec4 = fmt == 0 && pow2 && (d % 4) == 0 && (lda % 4) == 0 && (dpad % 4) == 0 &&
+                      (ldo % 4) == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)out & 7) == 0;
+    const float inv = pow2 ? 1.0f / mult : 0.f;
     if (fmt == 0)
         hipLaunchKernelGGL(quantize_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, A, rows,
-                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat);
+                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat, vec4, inv);
     else
         hipLaunchKernelGGL(quantize_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, A, rows,
-                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat);
+                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat, false, inv);
     return hipGetLastError();
 }
 

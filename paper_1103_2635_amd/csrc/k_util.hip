@@ -60,8 +60,10 @@ hipError_t launch_repack(const float* A, int64_t rows, int64_t lda, int32_t d, f
 // Squared norm of every row (16 lanes per row, fp32), and the largest row
 // norm as float bits through an integer atomic max (valid for non-negative
 // floats).  A bounded grid strides over the rows so that each workgroup
-// issues one atomic.  rowmap (optional) gives the source row of output row i.
-constexpr int kNormBlocks = 1024;
+// issues one atomic; 4,096 workgroups keep enough rows in flight for the
+// loop to stream at HBM rates.  rowmap (optional) gives the source row of
+// output row i.
+constexpr int kNormBlocks = 4096;
 
 // flags (optional, 3 words): [0] |= 2 (flags computed) and |= 1 if a value
 // is not an integer, [1] = max |value| as float bits, [2] |= 1 if a value is
@@ -69,7 +71,8 @@ constexpr int kNormBlocks = 1024;
 __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t rows, int64_t lda,
                                                         int32_t d, const int32_t* rowmap,
                                                         float* out, uint32_t* maxbits,
-                                                        uint32_t* flags, const int32_t* gate) {
+                                                        uint32_t* flags, const int32_t* gate,
+                                                        bool vec4) {
     if (gate && *gate == 0) return;  // uniform per launch
     __shared__ float wmax[4];
     __shared__ uint32_t wflag[4][3];
@@ -82,13 +85,29 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t 
         const int64_t src = rowmap ? rowmap[r] : r;
         const float* p = A + src * lda;
         float s = 0.f;
-        for (int f = sub; f < d; f += 16) {
-            const float v = p[f];
-            s = __builtin_fmaf(v, v, s);
-            if (flags) {
-                nonint |= (__builtin_rintf(v) != v) ? 1u : 0u;
-                neg |= v < 0.f ? 1u : 0u;
-                amax = fmaxf(amax, __builtin_fabsf(v));
+        if (vec4) {
+            // float4 runs 4 sub + 64 j (d, lda multiples of 4, rows 16-byte aligned)
+            for (int f = 4 * sub; f < d; f += 64) {
+                const f4 v = *(const f4*)(p + f);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    s = __builtin_fmaf(v[e], v[e], s);
+                    if (flags) {
+                        nonint |= (__builtin_rintf(v[e]) != v[e]) ? 1u : 0u;
+                        neg |= v[e] < 0.f ? 1u : 0u;
+                        amax = fmaxf(amax, __builtin_fabsf(v[e]));
+                    }
+                }
+            }
+        } else {
+            for (int f = sub; f < d; f += 16) {
+                const float v = p[f];
+                s = __builtin_fmaf(v, v, s);
+                if (flags) {
+                    nonint |= (__builtin_rintf(v) != v) ? 1u : 0u;
+                    neg |= v < 0.f ? 1u : 0u;
+                    amax = fmaxf(amax, __builtin_fabsf(v));
+                }
             }
         }
 #pragma unroll
@@ -137,8 +156,9 @@ hipError_t launch_row_norms(const float* A, int64_t rows, int64_t lda, int32_t d
     if (rows <= 0) return hipSuccess;
     int64_t blocks = (rows * 16 + 255) / 256;
     if (blocks > kNormBlocks) blocks = kNormBlocks;
+    const bool vec4 = (d % 4) == 0 && (lda % 4) == 0 && ((uintptr_t)A & 15) == 0;
     hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, rows, lda,
-                       d, rowmap, out, maxbits, flags, gate);
+                       d, rowmap, out, maxbits, flags, gate, vec4);
     return hipGetLastError();
 }
 
