@@ -1,3 +1,4 @@
+#include <algorithm>
 // k_rbc.hip -- kernels of the Random Ball Cover build and search that are not
 // distance tiles: row gathers, a stable counting sort (ownership lists and
 // query grouping), the list radii psi_r, the representative distances of
@@ -246,6 +247,46 @@ hipError_t launch_csort(const int32_t* keys, int64_t n, int32_t nk, int32_t* cnt
     if (offsets) {
         hipLaunchKernelGGL(csort_offsets_kernel, dim3((nk + 1 + 255) / 256), dim3(256), 0, st,
                            (const int32_t*)cnt, nk, nblk, n, offsets);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// ------------------------------------------------ grouping without order
+// Items 0..n-1 grouped by key: offsets[k] .. offsets[k + 1] hold the items
+// of key k, in no particular order inside a group (for groupings whose
+// consumers do not depend on that order).  cursor: nk int32 scratch.
+__global__ __launch_bounds__(256) void group_count_kernel(const int32_t* keys, int64_t n,
+                                                          int32_t* cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        atomicAdd(cnt + keys[i], 1);
+}
+
+__global__ __launch_bounds__(256) void group_fill_kernel(const int32_t* keys, int64_t n,
+                                                         const int32_t* offsets, int32_t* cursor,
+                                                         int32_t* perm) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const int32_t k = keys[i];
+        perm[offsets[k] + atomicAdd(cursor + k, 1)] = (int32_t)i;
+    }
+}
+
+hipError_t launch_group(const int32_t* keys, int64_t n, int32_t nk, int32_t* cursor,
+                        int32_t* perm, int32_t* offsets, hipStream_t st) {
+    hipError_t e;
+    if ((e = launch_fill_i32(offsets, nk + 1, 0, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(cursor, nk, 0, st)) != hipSuccess) return e;
+    const int64_t blocks = std::min<int64_t>(1024, (n + 255) / 256);
+    if (blocks > 0) {
+        hipLaunchKernelGGL(group_count_kernel, dim3((unsigned)blocks), dim3(256), 0, st, keys, n,
+                           offsets);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = launch_scan_total(offsets, nk, st)) != hipSuccess) return e;
+    if (blocks > 0) {
+        hipLaunchKernelGGL(group_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, keys, n,
+                           (const int32_t*)offsets, cursor, perm);
         e = hipGetLastError();
     }
     return e;

@@ -698,7 +698,7 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         w->ioffa = cv.take<int32_t>(nr + 1);
         // pass-1 items hold 16 queries (matrix path) or 256 (vector path)
         w->irepa = cv.take<int32_t>((m / 16 + nr + 1) * kMaxHomeSplit);
-        w->csa = cv.take<int32_t>(csort_scratch(m, (int32_t)nr));
+        w->csa = cv.take<int32_t>(nr);  // grouping cursors
         w->hval = cv.take<float>(m * kMaxHomeSplit * p.c);
         w->hidx = cv.take<int32_t>(m * kMaxHomeSplit * p.c);
         w->taud = cv.take<float>(m);
@@ -815,7 +815,9 @@ int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t 
     int rc;
     if ((rc = check(launch_nearest_rep(w.DR, ldd, (int32_t)m, nr, w.home, st), "nearest rep")))
         return rc;
-    if ((rc = check(launch_csort(w.home, m, nr, w.csa, w.qa, w.roffa, st), "group by home")))
+    // queries grouped by nearest representative; the order inside a group
+    // changes which queries share a pass-1 item, never a query's bound
+    if ((rc = check(launch_group(w.home, m, nr, w.csa, w.qa, w.roffa, st), "group by home")))
         return rc;
     const int ns = home_splits(ix, p);
     if ((rc = check(launch_items_from_offsets(w.roffa, nr, isize, w.ioffa, st, ns),

@@ -60,6 +60,10 @@ hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, cons
 // zeroed before item_rows), copied to srec in descending cost.
 hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int32_t* hist,
                              int32_t* srec, hipStream_t st);
+// Items grouped by key without a fixed order inside a group: offsets
+// [nk + 1] (total at offsets[nk]), perm [n]; cursor is nk int32 of scratch.
+hipError_t launch_group(const int32_t* keys, int64_t n, int32_t nk, int32_t* cursor,
+                        int32_t* perm, int32_t* offsets, hipStream_t st);
 hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
                                  hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.
