@@ -170,8 +170,11 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
             a0 = fmaxf(a0, wmax[w][0]);
             a1 = fmaxf(a1, wmax[w][1]);
         }
-        atomicMax(stat, __float_as_uint(a0));
-        atomicMax(stat + 1, __float_as_uint(a1));
+        // maxima only grow: skip the atomic when the word already holds more
+        if (__atomic_load_n(stat, __ATOMIC_RELAXED) < __float_as_uint(a0))
+            atomicMax(stat, __float_as_uint(a0));
+        if (__atomic_load_n(stat + 1, __ATOMIC_RELAXED) < __float_as_uint(a1))
+            atomicMax(stat + 1, __float_as_uint(a1));
     }
 }
 

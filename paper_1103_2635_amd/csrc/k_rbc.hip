@@ -791,8 +791,7 @@ hipError_t launch_tau_home(const float* hval, int32_t c, int32_t nsplit, int32_t
 // Unsorted lists are scanned whole.  taud null: every query has the bound
 // tconst (a range search radius).  One wavefront per item, grid-stride.
 // With rec non-null the item's record is written as well (representative,
-// first and end query position, row run, item) and its cost class (queries x
-// 32-row blocks, see item_cost) is counted in hist.
+// first and end query position, row run, item).
 // First position j in [L, R) of the ascending own[] with own[j] >= v
 // (after_equal: own[j] > v), or R: a 64-way search, each lane probing one
 // pivot per round, so a list of up to 262,144 rows needs three rounds of
@@ -830,7 +829,7 @@ __global__ __launch_bounds__(256) void item_rows_kernel(
     const int32_t* item_total, const int32_t* irep, const int32_t* ioff, const int32_t* roff,
     const int32_t* qlist, int32_t isize, const int32_t* list_off, const int32_t* lsorted,
     const float* own, const float* DR, int64_t ldd, const float* taud, double tconst,
-    double rel, int32_t* irows, int32_t* rec, int32_t* hist) {
+    double rel, int32_t* irows, int32_t* rec) {
     const int lane = threadIdx.x & 63;
     const int total = *item_total;
     const int nwave = gridDim.x * 4;
@@ -869,18 +868,30 @@ __global__ __launch_bounds__(256) void item_rows_kernel(
                 int32_t* o = rec + (int64_t)kItemRec * item;
                 *(int4*)o = make_int4(r, q_begin, q_end, lo);
                 *(int4*)(o + 4) = make_int4(hi, item, 0, 0);
-                atomicAdd(hist + item_cost(q_end - q_begin, lo, hi), 1);
             }
         }
     }
 }
 
-// hist[c] (items of cost class c) -> first queue position of class c, the
-// classes in descending order (one workgroup).
-__global__ __launch_bounds__(1024) void item_order_scan_kernel(int32_t* hist) {
+// The records in descending cost class, one workgroup: class counts in LDS,
+// their scan (largest class first), then each record copied to the next free
+// position of its class (the order inside a class is not fixed; every item
+// writes its own output slots).
+__global__ __launch_bounds__(1024) void item_order_kernel(const int32_t* item_total,
+                                                          const int32_t* rec, int32_t* srec) {
+    __shared__ int32_t hist[kCostBuckets];
     __shared__ int32_t part[1024];
     constexpr int kPer = kCostBuckets / 1024;
     const int t = threadIdx.x;
+    const int total = *item_total;
+    for (int c = t; c < kCostBuckets; c += 1024) hist[c] = 0;
+    __syncthreads();
+    for (int item = t; item < total; item += 1024) {
+        const int4 a = *(const int4*)(rec + (int64_t)kItemRec * item);
+        const int hi = rec[(int64_t)kItemRec * item + 4];
+        atomicAdd(&hist[item_cost(a.z - a.y, a.w, hi)], 1);
+    }
+    __syncthreads();
     // thread t owns classes kCostBuckets - 1 - kPer t - j (descending)
     int v[kPer], sum = 0;
 #pragma unroll
@@ -902,30 +913,19 @@ __global__ __launch_bounds__(1024) void item_order_scan_kernel(int32_t* hist) {
         hist[kCostBuckets - 1 - kPer * t - j] = base;
         base += v[j];
     }
-}
-
-// srec[position] = rec[item], positions taken per cost class (the order
-// inside a class is not fixed; every item writes its own output slots).
-__global__ __launch_bounds__(256) void item_order_scatter_kernel(const int32_t* item_total,
-                                                                 const int32_t* rec,
-                                                                 int32_t* base, int32_t* srec) {
-    const int total = *item_total;
-    for (int item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
+    __syncthreads();
+    for (int item = t; item < total; item += 1024) {
         const int4 a = *(const int4*)(rec + (int64_t)kItemRec * item);
         const int4 b = *(const int4*)(rec + (int64_t)kItemRec * item + 4);
-        const int pos = atomicAdd(base + item_cost(a.z - a.y, a.w, b.x), 1);
+        const int pos = atomicAdd(&hist[item_cost(a.z - a.y, a.w, b.x)], 1);
         *(int4*)(srec + (int64_t)kItemRec * pos) = a;
         *(int4*)(srec + (int64_t)kItemRec * pos + 4) = b;
     }
 }
 
-hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int32_t* hist,
-                             int32_t* srec, hipStream_t st) {
-    hipLaunchKernelGGL(item_order_scan_kernel, dim3(1), dim3(1024), 0, st, hist);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(item_order_scatter_kernel, dim3(256), dim3(256), 0, st, item_total, rec,
-                       hist, srec);
+hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int32_t* srec,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(item_order_kernel, dim3(1), dim3(1024), 0, st, item_total, rec, srec);
     return hipGetLastError();
 }
 
@@ -933,11 +933,10 @@ hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, cons
                             const int32_t* roff, const int32_t* qlist, int32_t isize,
                             const int32_t* list_off, const int32_t* lsorted, const float* own,
                             const float* DR, int64_t ldd, const float* taud, double tconst,
-                            double rel, int32_t* irows, hipStream_t st, int32_t* rec,
-                            int32_t* hist) {
+                            double rel, int32_t* irows, hipStream_t st, int32_t* rec) {
     hipLaunchKernelGGL(item_rows_kernel, dim3(1024), dim3(256), 0, st, item_total, irep, ioff,
                        roff, qlist, isize, list_off, lsorted, own, DR, ldd, taud, tconst, rel,
-                       irows, rec, hist);
+                       irows, rec);
     return hipGetLastError();
 }
 

@@ -135,9 +135,14 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t 
                 f1 = f1 > wflag[w][1] ? f1 : wflag[w][1];
                 f2 |= wflag[w][2];
             }
-            atomicOr(flags, f0 | 2u);
-            atomicMax(flags + 1, f1);
-            if (f2) atomicOr(flags + 2, f2);
+            // the words only grow, so a workgroup whose bits or maximum are
+            // already there skips its atomic (thousands of workgroups would
+            // otherwise serialise on the same three words)
+            if ((__atomic_load_n(flags, __ATOMIC_RELAXED) | f0 | 2u) !=
+                __atomic_load_n(flags, __ATOMIC_RELAXED))
+                atomicOr(flags, f0 | 2u);
+            if (__atomic_load_n(flags + 1, __ATOMIC_RELAXED) < f1) atomicMax(flags + 1, f1);
+            if (f2 && !(__atomic_load_n(flags + 2, __ATOMIC_RELAXED) & f2)) atomicOr(flags + 2, f2);
         }
     }
     if (maxbits) {
@@ -145,8 +150,10 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const float* A, int64_t 
         for (int off = 32; off >= 1; off >>= 1) nmax = fmaxf(nmax, __shfl_xor(nmax, off));
         if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = nmax;
         __syncthreads();
-        if (threadIdx.x == 0)
-            atomicMax(maxbits, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
+        if (threadIdx.x == 0) {
+            const uint32_t v = __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
+            if (__atomic_load_n(maxbits, __ATOMIC_RELAXED) < v) atomicMax(maxbits, v);
+        }
     }
 }
 

@@ -516,7 +516,6 @@ struct SearchWork {
     int32_t* irows = nullptr;    // 2 per pass-2 item: its row run
     int32_t* rec = nullptr;      // matrix path: kItemRec per pass-2 item, in item order
     int32_t* srec = nullptr;     // the same records, longest item first
-    int32_t* chist = nullptr;    // kCostBuckets: items per cost class
 };
 
 int64_t stage1_ld(int64_t nr) { return (nr + 3) / 4 * 4; }
@@ -706,7 +705,6 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         if (p.path == kPathMfma) {
             w->rec = cv.take<int32_t>(kItemRec * max_items);
             w->srec = cv.take<int32_t>(kItemRec * max_items);
-            w->chist = cv.take<int32_t>(kCostBuckets);
         }
     }
 }
@@ -912,16 +910,14 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                         "order queries")))
             return rc;
         if ((rc = check(launch_item_reps(w.ioff, nr, w.irep, st), "item reps"))) return rc;
-        if (w.rec && (rc = check(launch_fill_i32(w.chist, kCostBuckets, 0, st), "clear costs")))
-            return rc;
         if (p.two_pass &&
             (rc = check(launch_item_rows(w.ioff + nr, w.irep, w.ioff, w.roff, w.qlist, isize,
                                          ix->list_off, ix->lsorted, ix->own, w.DR, ldd, w.taud,
-                                         0.0, 2.0 * delta, w.irows, st, w.rec, w.chist),
+                                         0.0, 2.0 * delta, w.irows, st, w.rec),
                         "item rows")))
             return rc;
         // longest items first, so the persistent launch ends without a tail
-        if (w.rec && (rc = check(launch_item_order(w.ioff + nr, w.rec, w.chist, w.srec, st),
+        if (w.rec && (rc = check(launch_item_order(w.ioff + nr, w.rec, w.srec, st),
                                  "item order")))
             return rc;
         if (p.path == kPathLowp) {

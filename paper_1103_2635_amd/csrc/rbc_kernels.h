@@ -53,13 +53,12 @@ hipError_t launch_item_rows(const int32_t* item_total, const int32_t* irep, cons
                             const int32_t* roff, const int32_t* qlist, int32_t isize,
                             const int32_t* list_off, const int32_t* lsorted, const float* own,
                             const float* DR, int64_t ldd, const float* taud, double tconst,
-                            double rel, int32_t* irows, hipStream_t st, int32_t* rec = nullptr,
-                            int32_t* hist = nullptr);
+                            double rel, int32_t* irows, hipStream_t st, int32_t* rec = nullptr);
 // Longest-first order of the stage-2 items: the records rec[0 .. *item_total)
-// written by item_rows_kernel, counted per cost class in hist (kCostBuckets,
-// zeroed before item_rows), copied to srec in descending cost.
-hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int32_t* hist,
-                             int32_t* srec, hipStream_t st);
+// written by item_rows_kernel, copied to srec in descending cost class
+// (queries x 32-row blocks / 8).
+hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int32_t* srec,
+                             hipStream_t st);
 // Items grouped by key without a fixed order inside a group: offsets
 // [nk + 1] (total at offsets[nk]), perm [n]; cursor is nk int32 of scratch.
 hipError_t launch_group(const int32_t* keys, int64_t n, int32_t nk, int32_t* cursor,
