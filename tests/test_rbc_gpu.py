@@ -169,6 +169,22 @@ def test_seeded_representatives_and_errors(rbc):
     assert idx.shape == (0, 3)
 
 
+@pytest.mark.parametrize("m", [1024, 1008])
+def test_exact_search_query_count_multiple_of_16(rbc, orc, m):
+    """Query counts that are multiples of 16 take the 16-bytes-per-lane work
+    list; the answer is the brute-force one, and two calls agree bit for bit
+    (the grouping of pass 1 has no fixed order inside a group)."""
+    X, Q = datagen.database("sub8", 100000), datagen.queries("sub8", m)
+    reps = datagen.representatives("sub8", 100000, 316)
+    ix = rbc.rbc_build(_dev(X), 316, rep_idx=reps)
+    for k in (1, 10):
+        idx, dist, st = _search(rbc, ix, Q, k)
+        assert_knn_parity(idx, dist, Q, X, k, "l2", orc)
+        idx2, dist2, _ = _search(rbc, ix, Q, k)
+        assert np.array_equal(idx, idx2) and np.array_equal(dist, dist2)
+    ix.free()
+
+
 def test_exact_search_deterministic(rbc):
     X, Q = datagen.database("sub8", 50000), datagen.queries("sub8", 900)
     ix = rbc.rbc_build(_dev(X), 223, seed=2)
