@@ -4,7 +4,9 @@
 // Per row the kernel writes the quantised values (times `mult`, -2 for
 // queries, which is exact in both formats), the squared norm of the
 // quantised row ||x~||^2 (fp32), and an upper bound on the quantisation
-// error ||x - x~|| (its fp32 sum widened by the sum's relative error).  The
+// error ||x - x~|| (its fp32 sum widened by the sum's relative error).
+// Optionally (norm32, flags32) also the fp32 squared norm of the row itself
+// and the value flags of the row-norm kernel, from the same read.  The
 // largest row norm and the largest error go to stat words through integer
 // atomic maxima on non-negative float bits.
 //   stat[0] = max ||x~||, stat[1] = max ||x - x~||.
@@ -75,8 +77,12 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
                                                        int32_t d, float mult, void* out,
                                                        int64_t ldo, int32_t dpad, float* norm2,
                                                        float* err, uint8_t* scale_out,
-                                                       uint32_t* stat, bool vec4, float inv) {
+                                                       uint32_t* stat, bool vec4, float inv,
+                                                       float* norm32, uint32_t* flags32) {
     __shared__ float wmax[4][2];
+    __shared__ uint32_t wflag[4][3];
+    uint32_t nonint = 0, neg = 0;
+    float amax32 = 0.f;
     const int sub = threadIdx.x & 15;
     float nmax = 0.f, emax = 0.f;
     for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4; r < rows;
@@ -101,7 +107,7 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
             sexp = e;
             if (sub == 0) scale_out[r] = (uint8_t)(e + 127);
         }
-        float s2 = 0.f, e2 = 0.f;
+        float s2 = 0.f, e2 = 0.f, s32 = 0.f;
         if (FMT == 0 && vec4) {
             // float4 runs 4 sub + 64 j, four bf16 stored together; mult is
             // a power of two, so dividing by it is the exact product inv
@@ -111,6 +117,12 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
                 uint16_t b[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
+                    if (norm32) {
+                        s32 = __builtin_fmaf(v[e], v[e], s32);
+                        nonint |= (__builtin_rintf(v[e]) != v[e]) ? 1u : 0u;
+                        neg |= v[e] < 0.f ? 1u : 0u;
+                        amax32 = fmaxf(amax32, __builtin_fabsf(v[e]));
+                    }
                     b[e] = f32_to_bf16_rne(mult * v[e]);
                     const float deq = bf16_to_f32(b[e]) * inv;
                     s2 = __builtin_fmaf(deq, deq, s2);
@@ -125,6 +137,12 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
         } else
         for (int f = sub; f < dpad; f += 16) {
             const float v = f < d ? p[f] : 0.f;
+            if (norm32) {
+                s32 = __builtin_fmaf(v, v, s32);
+                nonint |= (__builtin_rintf(v) != v) ? 1u : 0u;
+                neg |= v < 0.f ? 1u : 0u;
+                amax32 = fmaxf(amax32, __builtin_fabsf(v));
+            }
             float deq;  // the quantised value of v (without mult)
             if (FMT == 0) {
                 const uint16_t b = f32_to_bf16_rne(mult * v);
@@ -144,7 +162,9 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
         for (int off = 8; off >= 1; off >>= 1) {
             s2 += __shfl_xor(s2, off, 16);
             e2 += __shfl_xor(e2, off, 16);
+            if (norm32) s32 += __shfl_xor(s32, off, 16);
         }
+        if (norm32 && sub == 0) norm32[r] = s32;
         // widen the error bound by the relative error of its fp32 sum
         const float eb = __builtin_sqrtf(e2 * (1.f + 4.f * (d + 2) * 5.9604645e-8f)) * (1.f + 1e-6f);
         if (sub == 0) {
@@ -164,6 +184,34 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
         wmax[threadIdx.x >> 6][1] = emax;
     }
     __syncthreads();
+    if (flags32) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            nonint |= __shfl_xor(nonint, off);
+            neg |= __shfl_xor(neg, off);
+            amax32 = fmaxf(amax32, __shfl_xor(amax32, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            wflag[threadIdx.x >> 6][0] = nonint;
+            wflag[threadIdx.x >> 6][1] = __float_as_uint(amax32);
+            wflag[threadIdx.x >> 6][2] = neg;
+        }
+    }
+    __syncthreads();
+    if (flags32 && threadIdx.x == 0) {
+        uint32_t f0 = 0, f1 = 0, f2 = 0;
+        for (int w = 0; w < 4; ++w) {
+            f0 |= wflag[w][0];
+            f1 = f1 > wflag[w][1] ? f1 : wflag[w][1];
+            f2 |= wflag[w][2];
+        }
+        // the same words and skip-if-present rule as the row-norm kernel
+        if ((__atomic_load_n(flags32, __ATOMIC_RELAXED) | f0 | 2u) !=
+            __atomic_load_n(flags32, __ATOMIC_RELAXED))
+            atomicOr(flags32, f0 | 2u);
+        if (__atomic_load_n(flags32 + 1, __ATOMIC_RELAXED) < f1) atomicMax(flags32 + 1, f1);
+        if (f2 && !(__atomic_load_n(flags32 + 2, __ATOMIC_RELAXED) & f2)) atomicOr(flags32 + 2, f2);
+    }
     if (threadIdx.x == 0) {
         float a0 = 0.f, a1 = 0.f;
         for (int w = 0; w < 4; ++w) {
@@ -181,6 +229,14 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* A, int64_t r
 hipError_t launch_quantize(int fmt, const float* A, int64_t rows, int64_t lda, int32_t d,
                            float mult, void* out, int64_t ldo, int32_t dpad, float* norm2,
                            float* err, uint8_t* scale_out, uint32_t* stat, hipStream_t st) {
+    return launch_quantize_norms(fmt, A, rows, lda, d, mult, out, ldo, dpad, norm2, err,
+                                 scale_out, stat, nullptr, nullptr, st);
+}
+
+hipError_t launch_quantize_norms(int fmt, const float* A, int64_t rows, int64_t lda, int32_t d,
+                                 float mult, void* out, int64_t ldo, int32_t dpad, float* norm2,
+                                 float* err, uint8_t* scale_out, uint32_t* stat, float* norm32,
+                                 uint32_t* flags32, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     int64_t blocks = (rows * 16 + 255) / 256;
     if (blocks > 4096) blocks = 4096;
@@ -192,10 +248,12 @@ hipError_t launch_quantize(int fmt, const float* A, int64_t rows, int64_t lda, i
     const float inv = pow2 ? 1.0f / mult : 0.f;
     if (fmt == 0)
         hipLaunchKernelGGL(quantize_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, A, rows,
-                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat, vec4, inv);
+                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat, vec4, inv,
+                           norm32, flags32);
     else
         hipLaunchKernelGGL(quantize_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, A, rows,
-                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat, false, inv);
+                           lda, d, mult, out, ldo, dpad, norm2, err, scale_out, stat, false, inv,
+                           norm32, flags32);
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include "../../include/rbc.h"
 #include "rbc_common.h"
 #include "rbc_host.h"
+#include "rbc_kernels.h"
 
 namespace rbc {
 
@@ -223,8 +224,9 @@ int run_bf_lowp(const BfPlan& p, const float* Q, int64_t m, int64_t ldq, const f
     uint32_t* ctr = (uint32_t*)w.counters;
     {
         KernelTimer kt("quantize", st);
-        if ((rc = hip_status(launch_quantize(fmt, Q, m, ldq, p.d, -2.0f, w.Qq, p.dq, p.dq, w.qn,
-                                             w.qerr, w.qscale, ctr + 14, st), "quantize Q")))
+        if ((rc = hip_status(launch_quantize_norms(fmt, Q, m, ldq, p.d, -2.0f, w.Qq, p.dq, p.dq,
+                                                   w.qn, w.qerr, w.qscale, ctr + 14, w.qn32,
+                                                   w.qflags32, st), "quantize Q")))
             return rc;
         if ((rc = hip_status(launch_quantize(fmt, X, n, ldx, p.d, 1.0f, w.Xq, p.dq, p.dq, w.xn,
                                              nullptr, w.xscale, ctr + 12, st), "quantize X")))

@@ -98,6 +98,10 @@ struct BfWork {
     float* qnc = nullptr;
     int32_t* qmap = nullptr;
     float* xn32 = nullptr;
+    // optional (set by the exact build): fp32 squared norms and value flags
+    // of the rows of Q, written by the low-precision path's quantiser
+    float* qn32 = nullptr;
+    uint32_t* qflags32 = nullptr;
     float* pval_c = nullptr;
     int32_t* pidx_c = nullptr;
 };

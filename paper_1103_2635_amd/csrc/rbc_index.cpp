@@ -282,8 +282,12 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
     int32_t *reps = nullptr, *owner = nullptr, *perm = nullptr, *cnt = nullptr;
     int64_t* own64 = nullptr;
     float* ownd = nullptr;
+    float* xn32 = nullptr;        // bf16 ownership: fp32 norms of X from the quantiser
+    uint32_t* xflags = nullptr;   // and the value flags (3 words)
     BfWork w;
     auto carve = [&](Carver& cv) {
+        xn32 = cv.take<float>(n);
+        xflags = cv.take<uint32_t>(4);
         reps = cv.take<int32_t>(n_r);
         owner = cv.take<int32_t>(n);
         perm = cv.take<int32_t>(n);
@@ -305,6 +309,11 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
         return rc;
     if ((rc = check(launch_gather_rows(X, ldx, d, reps, n_r, ix->R, ld, nullptr, st), "gather R")))
         return rc;
+    if (p.path == kPathLowp) {
+        w.qn32 = xn32;
+        w.qflags32 = xflags;
+        if ((rc = check(launch_fill_i32((int32_t*)xflags, 4, 0, st), "clear flags"))) return rc;
+    }
     if ((rc = run_bf(p, X, n, ldx, ix->R, n_r, ld, nullptr, nullptr, nullptr, own64, ownd, w,
                      nullptr, st)))
         return rc;
@@ -327,6 +336,11 @@ int build_exact(rbc_index* ix, const float* X, int64_t ldx, hipStream_t st) {
         if ((rc = check(launch_gather_norms(w.qn, perm, n, ix->xn, ix->norms_max,
                                             (const uint32_t*)w.counters + 5, ix->norms_max + 1,
                                             st), "norms")))
+            return rc;
+    } else if (p.path == kPathLowp) {
+        // the bf16 quantiser read X once for the copies, the norms and the flags
+        if ((rc = check(launch_gather_norms(xn32, perm, n, ix->xn, ix->norms_max, xflags,
+                                            ix->norms_max + 1, st), "norms")))
             return rc;
     } else if ((rc = check(launch_row_norms(ix->Xp, n, ld, d, nullptr, ix->xn, ix->norms_max, st,
                                             ix->norms_max + 1), "norms"))) {

@@ -63,6 +63,13 @@ hipError_t launch_item_order(const int32_t* item_total, const int32_t* rec, int3
 // [nk + 1] (total at offsets[nk]), perm [n]; cursor is nk int32 of scratch.
 hipError_t launch_group(const int32_t* keys, int64_t n, int32_t nk, int32_t* cursor,
                         int32_t* perm, int32_t* offsets, hipStream_t st);
+// launch_quantize that also writes the fp32 squared norm of every input row
+// (norm32[rows]) and its value flags (flags32[3], zeroed by the caller; see
+// launch_row_norms), reading each row once.
+hipError_t launch_quantize_norms(int fmt, const float* A, int64_t rows, int64_t lda, int32_t d,
+                                 float mult, void* out, int64_t ldo, int32_t dpad, float* norm2,
+                                 float* err, uint8_t* scale_out, uint32_t* stat, float* norm32,
+                                 uint32_t* flags32, hipStream_t st);
 hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
                                  hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.
