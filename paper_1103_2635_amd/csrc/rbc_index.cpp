@@ -667,7 +667,8 @@ int stage2_qb(const BfPlan& p) {
 }
 
 int home_splits(const rbc_index* ix, const BfPlan& p) {
-    const TileChoice tc = tile_choice(kTuneItems, p.ks, p.c);
+    // tuned choices belong to the fp32 matrix path; the vector path keeps the rule
+    const TileChoice tc = p.path == kPathMfma ? tile_choice(kTuneItems, p.ks, p.c) : TileChoice();
     if (tc.splits > 0) return std::min(tc.splits, kMaxHomeSplit);
     const int64_t per_list = ix->rows / std::max<int64_t>(ix->n_r, 1);
     return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxHomeSplit, per_list / 128));
@@ -980,7 +981,7 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
     a.stats = stats;
     a.irows = p.two_pass ? w.irows : nullptr;
     a.irec = w.srec;
-    const TileChoice tc = tile_choice(kTuneItems, p.ks, p.c);
+    const TileChoice tc = p.path == kPathMfma ? tile_choice(kTuneItems, p.ks, p.c) : TileChoice();
     a.shape = tc.shape;
     a.qb = stage2_qb(p);
     {
