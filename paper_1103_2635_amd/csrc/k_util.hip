@@ -225,6 +225,19 @@ __global__ __launch_bounds__(256) void item_rep_kernel(const int32_t* ioff, int3
     for (int i = ioff[r] + (threadIdx.x & 63); i < e; i += 64) irep[i] = r;
 }
 
+// a[i] = min(a[i], b[i]) (two upper bounds on the same distance).
+__global__ __launch_bounds__(256) void min_f32_kernel(float* a, const float* b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) a[i] = fminf(a[i], b[i]);
+}
+
+hipError_t launch_min_f32(float* a, const float* b, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(min_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b,
+                       n);
+    return hipGetLastError();
+}
+
 hipError_t launch_item_reps(const int32_t* ioff, int32_t nr, int32_t* irep, hipStream_t st) {
     if (nr <= 0) return hipSuccess;
     hipLaunchKernelGGL(item_rep_kernel, dim3((nr + 3) / 4), dim3(256), 0, st, ioff, nr, irep);

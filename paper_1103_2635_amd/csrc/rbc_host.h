@@ -72,6 +72,8 @@ struct BfPlan {
     bool one_pass;        // RBC_FLAG_ONE_PASS given
     bool two_pass;        // exact RBC search in two passes (set by the index's planner)
     int shape;            // fp32 matrix tile shape of the BF launch (kShape16 / kShape32)
+    bool lowp_seed;       // low-precision exact search: an fp32 pass over each query's
+                          // nearest list tightens the stage-2 shortlist seeds
 };
 
 struct BfWork {

@@ -530,6 +530,7 @@ struct SearchWork {
     int32_t* irows = nullptr;    // 2 per pass-2 item: its row run
     int32_t* rec = nullptr;      // matrix path: kItemRec per pass-2 item, in item order
     int32_t* srec = nullptr;     // the same records, longest item first
+    float* qn32 = nullptr;       // low-precision seeds: fp32 squared query norms
 };
 
 int64_t stage1_ld(int64_t nr) { return (nr + 3) / 4 * 4; }
@@ -705,7 +706,8 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
     // stage-2 items hold 64 or 32 queries (matrix path), 256 (vector path)
     const int64_t max_items = m * nr / 32 + nr + 1;
     w->irep = cv.take<int32_t>(max_items);
-    if (p.two_pass) {
+    if (p.lowp_seed) w->qn32 = cv.take<float>(m);
+    if (p.two_pass || p.lowp_seed) {
         w->home = cv.take<int32_t>(m);
         w->qa = cv.take<int32_t>(m);
         w->roffa = cv.take<int32_t>(nr + 1);
@@ -746,6 +748,10 @@ int search_plan(const rbc_index* ix, int64_t m, int64_t ldq, int32_t k,
     }
     p->two_pass = ix->mode == RBC_EXACT && (p->path == kPathMfma || p->path == kPathValu) &&
                   p->prune_eps == 0.0 && !p->one_pass;
+    // low precision (one pass): the fp32 matrix tile scans each query's
+    // nearest list first; rows of Q as whole float4 runs
+    p->lowp_seed = ix->mode == RBC_EXACT && p->path == kPathLowp && ix->metric == RBC_L2 &&
+                   (ix->d % 4) == 0 && (ldq % 4) == 0;
     return RBC_OK;
 }
 
@@ -819,7 +825,8 @@ int search_exact_lowp(const rbc_index* ix, const BfPlan& p, const float* Q, int6
 // shortlist becomes taud[q], an upper bound on the distance of q's k-th
 // nearest point (k points of X lie within it).
 int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t ldqk, int64_t m,
-                 int32_t k, SearchWork& w, double delta, int64_t ldd, hipStream_t st) {
+                 int32_t k, SearchWork& w, double delta, int64_t ldd, hipStream_t st,
+                 const float* qn = nullptr) {
     const int32_t nr = (int32_t)ix->n_r;
     // items of 16 queries on the matrix path (tile_l2_mfma_home), 256 on the
     // vector path
@@ -865,8 +872,8 @@ int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t 
                      "pass 1 (valu)");
     if (rc) return rc;
     const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
-    return check(launch_tau_home(w.hval, p.c, ns, k, (int32_t)m, mode, w.bf.qn, ix->norms_max,
-                                 ix->d, delta, w.taud, st), "k-th neighbour bound");
+    return check(launch_tau_home(w.hval, p.c, ns, k, (int32_t)m, mode, qn ? qn : w.bf.qn,
+                                 ix->norms_max, ix->d, delta, w.taud, st), "k-th neighbour bound");
 }
 
 // Exact search, Sec. 5.2: stage 1 (all representative distances), [pass 1
@@ -907,6 +914,19 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
             return rc;
         if ((rc = check(launch_keep_transpose(w.lrank, (int32_t)m, nr, w.keep_rq, st), "keep")))
             return rc;
+    }
+    if (p.lowp_seed) {
+        // low precision: an fp32 matrix-tile pass over each query's nearest
+        // list bounds the distance of its c-th nearest point (c rows lie
+        // within it); the smaller of that and gamma_c seeds the stage-2
+        // shortlists, so far fewer values are inserted into them
+        BfPlan p1 = p;
+        p1.path = kPathMfma;
+        if ((rc = check(launch_row_norms(Q, m, ldq, ix->d, nullptr, w.qn32, nullptr, st),
+                        "norms Q (fp32)")))
+            return rc;
+        if ((rc = search_pass1(ix, p1, Q, ldq, m, p.c, w, delta, ldd, st, w.qn32))) return rc;
+        if ((rc = check(launch_min_f32(w.gcup, w.taud, m, st), "seed bound"))) return rc;
     }
     {
         KernelTimer kt("worklist", st);

@@ -70,6 +70,8 @@ hipError_t launch_quantize_norms(int fmt, const float* A, int64_t rows, int64_t 
                                  float mult, void* out, int64_t ldo, int32_t dpad, float* norm2,
                                  float* err, uint8_t* scale_out, uint32_t* stat, float* norm32,
                                  uint32_t* flags32, hipStream_t st);
+// a[i] = min(a[i], b[i]) for i < n.
+hipError_t launch_min_f32(float* a, const float* b, int64_t n, hipStream_t st);
 hipError_t launch_keep_transpose(const int32_t* lrank, int32_t m, int32_t nr, uint8_t* keep_rq,
                                  hipStream_t st);
 // roff and ioff need nr + 1 entries; roff[nr] / ioff[nr] receive the totals.
