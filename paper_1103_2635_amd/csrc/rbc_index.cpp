@@ -527,6 +527,7 @@ struct SearchWork {
     float* hval = nullptr;       // m x c: pass-1 shortlists
     int32_t* hidx = nullptr;
     float* taud = nullptr;       // m: bound on the k-th neighbour distance
+    float* tauc = nullptr;       // m: bound on the c-th neighbour distance (two passes)
     int32_t* irows = nullptr;    // 2 per pass-2 item: its row run
     int32_t* rec = nullptr;      // matrix path: kItemRec per pass-2 item, in item order
     int32_t* srec = nullptr;     // the same records, longest item first
@@ -718,6 +719,7 @@ void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, S
         w->hval = cv.take<float>(m * kMaxHomeSplit * p.c);
         w->hidx = cv.take<int32_t>(m * kMaxHomeSplit * p.c);
         w->taud = cv.take<float>(m);
+        if (p.two_pass) w->tauc = cv.take<float>(m);
         w->irows = cv.take<int32_t>(2 * max_items);
         if (p.path == kPathMfma) {
             w->rec = cv.take<int32_t>(kItemRec * max_items);
@@ -826,7 +828,7 @@ int search_exact_lowp(const rbc_index* ix, const BfPlan& p, const float* Q, int6
 // nearest point (k points of X lie within it).
 int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t ldqk, int64_t m,
                  int32_t k, SearchWork& w, double delta, int64_t ldd, hipStream_t st,
-                 const float* qn = nullptr) {
+                 const float* qn = nullptr, float* tauc = nullptr) {
     const int32_t nr = (int32_t)ix->n_r;
     // items of 16 queries on the matrix path (tile_l2_mfma_home), 256 on the
     // vector path
@@ -872,8 +874,17 @@ int search_pass1(const rbc_index* ix, const BfPlan& p, const float* Qk, int64_t 
                      "pass 1 (valu)");
     if (rc) return rc;
     const int mode = p.path == kPathMfma ? 0 : (ix->metric == RBC_L2 ? 1 : 2);
-    return check(launch_tau_home(w.hval, p.c, ns, k, (int32_t)m, mode, qn ? qn : w.bf.qn,
-                                 ix->norms_max, ix->d, delta, w.taud, st), "k-th neighbour bound");
+    if ((rc = check(launch_tau_home(w.hval, p.c, ns, k, (int32_t)m, mode, qn ? qn : w.bf.qn,
+                                    ix->norms_max, ix->d, delta, w.taud, st),
+                    "k-th neighbour bound")))
+        return rc;
+    // the same shortlists bound the c-th neighbour distance too (c rows lie
+    // within their c-th value): the stage-2 shortlists start from it
+    if (tauc && (rc = check(launch_tau_home(w.hval, p.c, ns, p.c, (int32_t)m, mode,
+                                            qn ? qn : w.bf.qn, ix->norms_max, ix->d, delta,
+                                            tauc, st), "c-th neighbour bound")))
+        return rc;
+    return RBC_OK;
 }
 
 // Exact search, Sec. 5.2: stage 1 (all representative distances), [pass 1
@@ -904,7 +915,9 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
         (rc = check(launch_row_norms(Qk, m, ldqk, p.d, nullptr, w.bf.qn, nullptr, st,
                                      (uint32_t*)w.bf.counters + 5), "norms Q")))
         return rc;
-    if (p.two_pass && (rc = search_pass1(ix, p, Qk, ldqk, m, k, w, delta, ldd, st))) return rc;
+    if (p.two_pass &&
+        (rc = search_pass1(ix, p, Qk, ldqk, m, k, w, delta, ldd, st, nullptr, w.tauc)))
+        return rc;
     {
         KernelTimer kt("prune", st);
         if ((rc = check(launch_prune(w.DR, ldd, (int32_t)m, nr, k, p.c, delta, ix->psi,
@@ -913,6 +926,10 @@ int search_exact(const rbc_index* ix, const BfPlan& p, const float* Q, int64_t m
                         "prune")))
             return rc;
         if ((rc = check(launch_keep_transpose(w.lrank, (int32_t)m, nr, w.keep_rq, st), "keep")))
+            return rc;
+        // stage-2 shortlists start from the smaller of gamma_c and the pass-1
+        // bound on the c-th neighbour distance
+        if (p.two_pass && (rc = check(launch_min_f32(w.gcup, w.tauc, m, st), "seed bound")))
             return rc;
     }
     if (p.lowp_seed) {
