@@ -81,10 +81,11 @@ __global__ __launch_bounds__(256, (Mfma32qOcc<KS, C>::value)) void tile_l2_mfma_
 // Pass 1 of the two-pass search: the item body over the nearest lists, with
 // 16-query items (one query block per wavefront): a nearest list holds few
 // queries (about m / n_r), so wider items would mostly score empty slots.
+// Each lane inserts its own MFMA outputs into one of four shortlists per
+// query (scan_rows_direct), so the kernel needs no LDS.
 template <int KS, int C>
 __global__ __launch_bounds__(256, (MfmaOcc<KS, C>::value)) void tile_l2_mfma_home(TileArgs a) {
-    __shared__ __attribute__((aligned(16))) float tbuf[4][64 * kTStride];
-    tile_items_body<Fp32Policy<KS>, C, 1>(a, tbuf[threadIdx.x >> 6]);
+    tile_items_body<Fp32Policy<KS>, C, 1>(a, nullptr);  // no transpose, no LDS
 }
 
 // The 32x32x2 shape (tile_mfma32.h): no LDS, two shortlists per lane.

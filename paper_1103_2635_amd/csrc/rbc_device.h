@@ -124,6 +124,26 @@ struct TopC {
     }
 };
 
+// Insert (x, id) into a sorted shortlist in (value, row) order; merging two
+// shortlists this way keeps the c smallest values of their union.
+template <int C>
+__device__ __forceinline__ void insert_lex(TopC<C>& t, float x, int32_t id) {
+    bool lt[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) lt[j] = x < t.v[j] || (x == t.v[j] && id < t.i[j]);
+    if (!lt[C - 1]) return;
+#pragma unroll
+    for (int j = C - 1; j > 0; --j) {
+        const float nv = lt[j - 1] ? t.v[j - 1] : (lt[j] ? x : t.v[j]);
+        const int32_t ni = lt[j - 1] ? t.i[j - 1] : (lt[j] ? id : t.i[j]);
+        t.v[j] = nv;
+        t.i[j] = ni;
+    }
+    t.v[0] = lt[0] ? x : t.v[0];
+    t.i[0] = lt[0] ? id : t.i[0];
+}
+
+
 // Representative of work item `item` (item mode): the last r with
 // ioff[r] <= item (representatives without items have ioff[r] == ioff[r + 1]).
 __device__ __forceinline__ int item_rep(const TileArgs& a, int item) {

@@ -60,24 +60,6 @@ __device__ __forceinline__ void load_x32(f4 (&xf)[2 * KS], const TileArgs& a, in
     load_half_row<KS>(xf, a.X + (int64_t)row * a.ldx, a.d, h, 1.0f);
 }
 
-// Merge of two sorted shortlists into the first, in (value, row) order.
-template <int C>
-__device__ __forceinline__ void insert_lex(TopC<C>& t, float x, int32_t id) {
-    bool lt[C];
-#pragma unroll
-    for (int j = 0; j < C; ++j) lt[j] = x < t.v[j] || (x == t.v[j] && id < t.i[j]);
-    if (!lt[C - 1]) return;
-#pragma unroll
-    for (int j = C - 1; j > 0; --j) {
-        const float nv = lt[j - 1] ? t.v[j - 1] : (lt[j] ? x : t.v[j]);
-        const int32_t ni = lt[j - 1] ? t.i[j - 1] : (lt[j] ? id : t.i[j]);
-        t.v[j] = nv;
-        t.i[j] = ni;
-    }
-    t.v[0] = lt[0] ? x : t.v[0];
-    t.i[0] = lt[0] ? id : t.i[0];
-}
-
 // Lane l holds, per query block qb, the shortlist of query 32 qb + (l mod 32)
 // over its half of the rows.  Lane l ends with the merged list of query l:
 // its own list of block h and the list of the same query kept by lane l ^ 32.

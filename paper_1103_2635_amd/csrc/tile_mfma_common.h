@@ -185,6 +185,75 @@ __device__ __forceinline__ void scan_rows(const typename P::QFrag (&qf)[QB][P::k
     }
 }
 
+// One query block per wavefront (QB = 1): lane (g, c16) holds the values of
+// rows base + 16 rb + 4 g + i for query c16, and pushes them into its own
+// shortlist, one of four per query (one per g), with no transpose: all 64
+// lanes insert, 8 values each.  merge_groups joins the four at the end.
+template <class P, int C>
+__device__ __forceinline__ void scan_block_direct(const typename P::QFrag (&qf)[1][P::kBlocks],
+                                                  const typename P::XFrag (&x)[2][P::kBlocks],
+                                                  const f4 (&nr)[2], int base, int r1,
+                                                  TopC<C>& top, int g) {
+    f4 acc[2][1];
+    tile_step<P, 1>(acc, qf, x, nr, base, r1, g);
+    const float m0 = fminf(fminf(acc[0][0][0], acc[0][0][1]), fminf(acc[0][0][2], acc[0][0][3]));
+    const float m1 = fminf(fminf(acc[1][0][0], acc[1][0][1]), fminf(acc[1][0][2], acc[1][0][3]));
+    if (fminf(m0, m1) < top.worst()) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) top.push(acc[rb][0][i], base + 16 * rb + 4 * g + i);
+    }
+}
+
+template <class P, int C>
+__device__ __forceinline__ void scan_rows_direct(const typename P::QFrag (&qf)[1][P::kBlocks],
+                                                 const TileArgs& a, int r0, int r1, TopC<C>& top,
+                                                 int lane) {
+    const int g = lane >> 4;
+    const int c16 = lane & 15;
+    typename P::XFrag xa[2][P::kBlocks], xb[2][P::kBlocks];
+    f4 na[2], nb[2];
+    load_xfrags<P>(xa, a, r0, c16, g);
+    load_norms(na, a.xn, r0, r1, g);
+    int base = r0;
+    for (;;) {
+        int next = base + kRowsMfma;
+        int nbase = next < r1 ? next : base;
+        load_xfrags<P>(xb, a, nbase, c16, g);
+        load_norms(nb, a.xn, nbase, r1, g);
+        __builtin_amdgcn_sched_barrier(0);
+        scan_block_direct<P, C>(qf, xa, na, base, r1, top, g);
+        base = next;
+        if (base >= r1) break;
+        next = base + kRowsMfma;
+        nbase = next < r1 ? next : base;
+        load_xfrags<P>(xa, a, nbase, c16, g);
+        load_norms(na, a.xn, nbase, r1, g);
+        __builtin_amdgcn_sched_barrier(0);
+        scan_block_direct<P, C>(qf, xb, nb, base, r1, top, g);
+        base = next;
+        if (base >= r1) break;
+    }
+}
+
+// The four shortlists of query c16 (lanes c16, c16 + 16, c16 + 32, c16 + 48)
+// merged; lanes 0 .. 15 end with the merged list of their query.
+template <int C>
+__device__ __forceinline__ void merge_groups(TopC<C>& top) {
+#pragma unroll
+    for (int mask = 16; mask <= 32; mask <<= 1) {
+        TopC<C> o;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            o.v[j] = __shfl_xor(top.v[j], mask);
+            o.i[j] = __shfl_xor(top.i[j], mask);
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j) insert_lex<C>(top, o.v[j], o.i[j]);
+    }
+}
+
 // BF mode: grid (query blocks of 256, database splits), or, with a device-side
 // query count, a 1-D grid laid out by dev_split.
 template <class P, int C>
@@ -266,7 +335,17 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         const bool valid = lane < kQ && p < q_end;
         const int q = a.qlist[valid ? p : q_end - 1];
         TopC<C> top;
-        if (a.tau) top.seed(a.tau[q]); else top.init();
+        if constexpr (QB == 1) {
+            // every lane keeps a shortlist of query c16 (see scan_block_direct);
+            // lanes of empty query slots never insert
+            if (q_begin + c16 >= q_end) top.seed(-RBC_INF);
+            else if (a.tau) top.seed(a.tau[qrow[0]]);
+            else top.init();
+        } else if (a.tau) {
+            top.seed(a.tau[q]);
+        } else {
+            top.init();
+        }
         int r0 = a.list_off[r], r1 = a.list_off[r + 1];
         if (a.irows) {
             r0 = __builtin_amdgcn_readfirstlane(a.irows[2 * (int64_t)item]);
@@ -279,7 +358,12 @@ __device__ __forceinline__ void tile_items_body(const TileArgs& a, float* tbuf_w
         // next ticket: issued after this item's metadata loads (memory
         // counters retire in issue order), consumed at the next iteration
         if (lane == 0) ticket = atomicAdd(a.item_queue, 1);
-        if (r0 < r1) scan_rows<P, C, QB>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
+        if constexpr (QB == 1) {
+            if (r0 < r1) scan_rows_direct<P, C>(qf, a, r0, r1, top, lane);
+            merge_groups<C>(top);
+        } else if (r0 < r1) {
+            scan_rows<P, C, QB>(qf, a, r0, r1, valid, top, tbuf_wave, lane);
+        }
         if (valid) {
             const int64_t pair = a.lrank ? (int64_t)a.qoff[q] + a.lrank[(int64_t)q * a.n_r + r]
                                          : (int64_t)q * (a.isplit > 1 ? a.isplit : 1) + split;
