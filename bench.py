@@ -33,10 +33,11 @@ FP32_MFMA_PEAK_TF = 157.3   # MI355X dense fp32 matrix peak
 ALU_PEAK_TOPS = 78.6        # fp32 VALU lane-operations per second (157.3 TFLOP/s counts an FMA as 2)
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's counts), or None when
-    there is no summary or the kernel's sources changed since it was taken."""
+def profiled_traffic(kernel, grid_threads=None):
+    """HBM bytes per launch of `kernel` (launched with grid_threads work-items,
+    when given) from the committed rocprofv3 summaries (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy's counts), or None when there is no such
+    summary or the kernel's sources changed since it was taken."""
     import glob
     import hashlib
 
@@ -47,6 +48,8 @@ def profiled_traffic(kernel):
                 continue
             rec = json.loads(line)
             if rec.get("kernel") != kernel:
+                continue
+            if grid_threads is not None and rec.get("grid_threads") != grid_threads:
                 continue
             h = hashlib.sha256()
             try:
@@ -214,10 +217,13 @@ def main():
     # of its list that the two-pass bound leaves (pairs); that is the work
     roofline = roof(per_pair * pairs, tile_avg)
     kname = "tile_valu_items"
+    tuned = tuning.get("rbc_search", {})
     if metric == "l2":
-        kname = ("tile_l2_mfma32_items" if tuning.get("rbc_search", {}).get("shape") == 32
-                 else "tile_l2_mfma_items")
-    roofline["traffic"] = (profiled_traffic("void rbc::%s<4, 4>(rbc::TileArgs)" % kname)
+        kname = ("tile_l2_mfma32_items" if tuned.get("shape") == 32 else
+                 "tile_l2_mfma_items32q" if tuned.get("item_queries") == 32 else
+                 "tile_l2_mfma_items")
+    roofline["traffic"] = (profiled_traffic("void rbc::%s<4, 4>(rbc::TileArgs)" % kname,
+                                            256 * tuned.get("blocks", 1024))
                            if (metric, k) == ("l2", 1) else None)
     roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)"
     roofline["kernel"] = kname + " (RBC stage 2)"
@@ -228,8 +234,9 @@ def main():
     bf_avg = bf_tile_ms / max(bf_tile_n, 1)
     bf_roof = roof(per_pair * m * n, bf_avg)
     bf_roof["avg_ms"] = round(bf_avg, 4)
-    bf_roof["kernel"] = "tile_l2_mfma (brute force)" if metric == "l2" else "tile_valu (brute force)"
-    bf_roof["traffic"] = (profiled_traffic("void rbc::tile_l2_mfma<4, 4>(rbc::TileArgs)")
+    bf_k = "tile_l2_mfma32" if tuning.get("bf_search", {}).get("shape") == 32 else "tile_l2_mfma"
+    bf_roof["kernel"] = ("%s (brute force)" % bf_k) if metric == "l2" else "tile_valu (brute force)"
+    bf_roof["traffic"] = (profiled_traffic("void rbc::%s<4, 4>(rbc::TileArgs)" % bf_k)
                           if (metric, k) == ("l2", 1) else None)
 
     extra = {}
