@@ -307,7 +307,7 @@ int rbc_timer_read(const char* name, double* total_ms, int64_t* launches);
  * rbc_autotune_search runs the given rbc_search once untimed and three times
  * timed (HIP events on hip_stream) under each candidate (16x16 with 64- or
  * 32-query stage-2 items, or 32x32; x 512 / 1024 / 2048 workgroups x pass-1
- * splits by the size rule or 2),
+ * splits by the size rule or 4),
  * rbc_autotune_bf likewise for bf_search (2 shapes); the fastest is kept,
  * process-wide, for every later call with the
  * same launch kind, 16-feature slab count (ceil(d / 16)) and shortlist

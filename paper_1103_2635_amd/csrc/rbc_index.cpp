@@ -672,8 +672,12 @@ int home_splits(const rbc_index* ix, const BfPlan& p) {
     // tuned choices belong to the fp32 matrix path; the vector path keeps the rule
     const TileChoice tc = p.path == kPathMfma ? tile_choice(kTuneItems, p.ks, p.c) : TileChoice();
     if (tc.splits > 0) return std::min(tc.splits, kMaxHomeSplit);
+    // untuned: about 400 rows per range on the matrix path (two ranges for
+    // lists of 1,000 rows measured fastest among 1 .. 8), 128 on the vector
+    // path, whose rows cost more
     const int64_t per_list = ix->rows / std::max<int64_t>(ix->n_r, 1);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxHomeSplit, per_list / 128));
+    const int64_t per_range = p.path == kPathMfma ? 400 : 128;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxHomeSplit, per_list / per_range));
 }
 
 void carve_search(const rbc_index* ix, const BfPlan& p, int64_t m, Carver& cv, SearchWork* w) {

@@ -150,7 +150,7 @@ int rbc_autotune_search(const rbc_index* ix, const float* Q, int64_t m, int64_t 
         std::vector<TileChoice> cands;
         for (int v = 0; v < 3; ++v)
             for (int blocks : {kItemBlocks / 2, kItemBlocks, 2 * kItemBlocks})
-                for (int splits : {0, 2}) {
+                for (int splits : {0, 4}) {
                     TileChoice t;
                     t.shape = v == 2 ? kShape32 : kShape16;
                     t.qb = v == 1 ? 2 : 4;
