@@ -179,21 +179,22 @@ __global__ __launch_bounds__(1024) void os_sort_kernel(const float* X, int64_t l
         }
     }
     __syncthreads();
+    // bitonic network, one compare-exchange pair per thread and pass: pair t
+    // joins element i (t with a zero bit inserted at j) and i + j
     for (int kk = 2; kk <= size; kk <<= 1) {
         for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < size; i += blockDim.x) {
-                const int p = i ^ j;
-                if (p > i) {
-                    const bool up = (i & kk) == 0;
-                    const bool gt = key[i] > key[p] || (key[i] == key[p] && id[i] > id[p]);
-                    if (gt == up) {
-                        const double tk = key[i];
-                        key[i] = key[p];
-                        key[p] = tk;
-                        const int32_t ti = id[i];
-                        id[i] = id[p];
-                        id[p] = ti;
-                    }
+            for (int t = threadIdx.x; t < (size >> 1); t += blockDim.x) {
+                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const int p = i | j;
+                const bool up = (i & kk) == 0;
+                const bool gt = key[i] > key[p] || (key[i] == key[p] && id[i] > id[p]);
+                if (gt == up) {
+                    const double tk = key[i];
+                    key[i] = key[p];
+                    key[p] = tk;
+                    const int32_t ti = id[i];
+                    id[i] = id[p];
+                    id[p] = ti;
                 }
             }
             __syncthreads();

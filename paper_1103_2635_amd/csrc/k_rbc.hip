@@ -974,17 +974,20 @@ __global__ __launch_bounds__(1024) void seg_sort_kernel(const int32_t* off, int3
         key[i] = kv;
     }
     __syncthreads();
+    // bitonic network; thread t takes compare-exchange pairs t, t + 1024, ...
+    // of each stage: pair t joins element i (t with a zero bit inserted at j)
+    // and i + j, so every thread has work in every stage
+    const int half = size >> 1;
     for (int kk = 2; kk <= size; kk <<= 1) {
         for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < size; i += blockDim.x) {
-                const int p = i ^ j;
-                if (p > i) {
-                    const bool up = (i & kk) == 0;
-                    const uint64_t a = key[i], c = key[p];
-                    if ((a > c) == up) {
-                        key[i] = c;
-                        key[p] = a;
-                    }
+            for (int t = threadIdx.x; t < half; t += blockDim.x) {
+                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const int p = i | j;
+                const bool up = (i & kk) == 0;
+                const uint64_t a = key[i], c = key[p];
+                if ((a > c) == up) {
+                    key[i] = c;
+                    key[p] = a;
                 }
             }
             __syncthreads();
