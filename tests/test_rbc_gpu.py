@@ -146,6 +146,24 @@ def test_exact_search_duplicates_and_integer_ties(rbc, orc):
             assert_knn_parity(idx, dist, Q, X, k, metric, orc, ref=(ref_i, ref_d))
 
 
+def test_matrix_path_integer_ties_two_pass_seed(rbc, orc):
+    """Matrix-core path (L2, d = 16) on small-integer data with many exactly
+    equal distances: the stage-2 shortlists start from the pass-1 bound on
+    the c-th neighbour distance, which on such data often equals the k-th.
+    The ids must still be those of the FP64 oracle, (distance, id) order."""
+    rng = np.random.default_rng(12)
+    base = rng.integers(0, 4, size=(1500, 16)).astype(np.float32)
+    X = np.concatenate([base, base[:700]])
+    Q = rng.integers(0, 4, size=(300, 16)).astype(np.float32)
+    reps = datagen.random_reps(X.shape[0], 48, seed=13)
+    ix = rbc.rbc_build(_dev(X), 48, rep_idx=reps)
+    for k in (1, 5, 10):
+        idx, dist, st = _search(rbc, ix, Q, k)
+        ref_i, ref_d = orc.bf_knn(Q, X, k, "l2")
+        assert np.array_equal(idx, ref_i)
+        assert_knn_parity(idx, dist, Q, X, k, "l2", orc, ref=(ref_i, ref_d))
+
+
 def test_seeded_representatives_and_errors(rbc):
     import torch
 
